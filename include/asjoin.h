@@ -1,0 +1,173 @@
+/*
+ * libasjoin -- signature-accelerated hash equi-join on one MI355X (gfx950).
+ *
+ * Computes T = Join(R, S) on the predicate r = s between two relations of
+ * variable-length byte-string join attributes, following Mokadem, Hameurlain,
+ * Morvan, "Equi join query acceleration using algebraic signatures":
+ *
+ *   Section 2     R (m tuples) is the smaller relation; a hash table is built
+ *                 on R and probed with every tuple of S; matching tuples are
+ *                 concatenated into the result T.
+ *   Section 3.1   the algebraic signature: GF(2^f) symbols, the n-symbol
+ *                 signature sig_alpha(P) = (sum_i p_i alpha^(j i))_{j=1..n},
+ *                 4 bytes as two GF(2^16) components.
+ *   Section 3.2   Figure 2: sign every r, Build(R, H_sign), sign every s,
+ *                 Probe(H_sign, s), output on signature match, Materialize(T).
+ *
+ * Unlike the paper, every signature match is also verified byte by byte
+ * (unless ASJ_NO_VERIFY), so the output is exactly the equi-join.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - All array arguments are DEVICE pointers on the current HIP device unless
+ *   stated otherwise.  The caller owns every input and output buffer.
+ * - Calls are asynchronous on `stream` (0 = the legacy default stream).  The
+ *   return value reports host-side validation and launch errors only;
+ *   conditions found on the device are reported through the device counters
+ *   described with each call, or through asj_table_status().
+ * - Return codes: ASJ_OK (0) or a negative ASJ_E* code; asj_strerror() names
+ *   them.  No C++ exception and no abort crosses this interface.
+ * - Thread safety: calls on different streams may run concurrently; a table
+ *   is read-only after asj_build() and may be probed from several streams.
+ */
+#ifndef ASJOIN_H
+#define ASJOIN_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define ASJ_OK 0
+#define ASJ_EINVAL (-1)       /* bad argument (null pointer, negative size, bad parameters) */
+#define ASJ_ENOMEM (-2)       /* device allocation failed */
+#define ASJ_EOVERFLOW (-3)    /* more result pairs than the caller's capacity (see asj_probe) */
+#define ASJ_ETABLEFULL (-4)   /* the hash table had no free slot for a build row */
+#define ASJ_EHIP (-5)         /* a HIP runtime call failed */
+#define ASJ_EUNSUPPORTED (-6) /* parameter combination not implemented on the GPU */
+
+/* ---- option flags (asj_opts.flags) ---- */
+#define ASJ_NO_VERIFY 0x1u /* paper-literal output (Section 3.2, Figure 2): every pair whose
+                              signatures are equal, without comparing the key bytes */
+#define ASJ_PLAIN 0x2u     /* baseline simple hash join (Section 2): a full-key multiplicative
+                              hash instead of the signature; every occupied slot on the probe
+                              path is compared by length and bytes (no stored fingerprint) */
+
+/* A relation's join attributes: key k is data[offsets[k] .. offsets[k+1]).
+ * offsets must be non-decreasing (k = 0..n).  The library reads only
+ * 4-byte-aligned words that hold at least one byte of some key, so `data`
+ * needs no padding.  ids[k] is the tuple id written to the output; ids ==
+ * NULL means the row index k.  n < 2^31.  All three pointers are device
+ * pointers (data may be NULL when every key is empty). */
+typedef struct asj_keys {
+    const uint8_t *data;
+    const int64_t *offsets;
+    const int32_t *ids;
+    int64_t n;
+} asj_keys;
+
+/* One result tuple of T: the ids of the matching build and probe rows. */
+typedef struct asj_pair {
+    int32_t r_id;
+    int32_t s_id;
+} asj_pair;
+
+/* Signature parameters (Section 3.1): symbol width f in bits and the number
+ * of components n; f * nsym <= 32.  Supported: {16, 2} (the paper's 4-byte
+ * sig_alpha,2 over GF(2^16), the default), {16, 1}, {8, 4}, {8, 2}. */
+typedef struct asj_sig_params {
+    int32_t f;
+    int32_t nsym;
+} asj_sig_params;
+
+/* Join options.  sig = {0, 0} means {16, 2}; load_factor <= 0 means 0.5
+ * (table capacity = next power of two >= m / load_factor, at least 64). */
+typedef struct asj_opts {
+    asj_sig_params sig;
+    float load_factor;
+    uint32_t flags;
+} asj_opts;
+
+/* Opaque build-side hash table H_sign (Section 3.2): an open-addressing
+ * multimap of 64-bit slots (signature << 32 | build row), linear probing.
+ * It owns its slot array and BORROWS the build relation's data, offsets
+ * and ids, which the caller keeps alive and unchanged until asj_table_free. */
+typedef struct asj_table asj_table;
+
+/* Algebraic signature of every key (Section 3.1).
+ *   keys     the relation (device arrays, see asj_keys)
+ *   p        signature parameters; {0,0} means {16,2}
+ *   sig_out  device uint32[keys->n]; component j is stored in bits
+ *            [(j-1)f, jf): for {16,2}, sig = s1 | s2 << 16
+ * Errors: ASJ_EINVAL (null/negative), ASJ_EUNSUPPORTED (parameters),
+ * ASJ_EHIP (launch). */
+int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hipStream_t stream);
+
+/* Build phase (Section 3.2, Figure 2: pre-calculate Sign(r), Build(R, H_sign)).
+ *   r          build relation (borrowed by the table, see asj_table)
+ *   opts       may be NULL (defaults)
+ *   table_out  receives the new table (host pointer to a handle)
+ * The slot array is allocated stream-ordered on `stream`.  Whether every row
+ * found a slot is known only on the device: asj_table_status() reports it.
+ * Errors: ASJ_EINVAL, ASJ_EUNSUPPORTED, ASJ_ENOMEM, ASJ_EHIP. */
+int asj_build(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t stream);
+
+/* Probe phase (Section 3.2, Figure 2: Probe(H_sign, s) for every s, output
+ * the matching tuples, Materialize(T)).
+ *   t           table from asj_build (its build stream's work must be
+ *               ordered before this call, e.g. the same stream)
+ *   s           probe relation
+ *   out         device asj_pair[out_cap] (may be NULL when out_cap == 0)
+ *   out_cap     capacity of `out` in pairs
+ *   out_count   device int64[1]; set to |T|, the full number of result
+ *               pairs, even when it exceeds out_cap (pairs past out_cap are
+ *               not written; call again with a larger buffer)
+ *   cand_count  device int64[1] or NULL; set to the number of (r, s) pairs
+ *               whose signatures are equal (the candidates verified), or to
+ *               the number of slots compared for ASJ_PLAIN tables
+ * The order of the pairs in `out` is unspecified.
+ * Errors: ASJ_EINVAL, ASJ_EHIP. */
+int asj_probe(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
+              int64_t *cand_count, hipStream_t stream);
+
+/* asj_build + asj_probe + asj_table_free in one stream-ordered call (the
+ * whole of Figure 2).  Arguments as for those calls.  A full table is
+ * reported as |T| = -1 in *out_count. */
+int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+             int64_t *out_count, int64_t *cand_count, hipStream_t stream);
+
+/* Waits for the table's build work and returns ASJ_OK or ASJ_ETABLEFULL. */
+int asj_table_status(const asj_table *t);
+
+/* Number of slots of the table (a power of two), or -1 for NULL. */
+int64_t asj_table_capacity(const asj_table *t);
+
+/* Releases the table (stream-ordered on its build stream).  NULL is a no-op. */
+int asj_table_free(asj_table *t);
+
+/* Static description of a return code. */
+const char *asj_strerror(int code);
+
+/* ---- measurement support (not part of the join) ---- */
+
+/* Per-kernel timing of the last asj_join()/asj_build()/asj_probe() issued
+ * by this thread while timing is on: HIP events are recorded around each
+ * kernel on the call's stream.  asj_timing_read() synchronizes with the
+ * last recorded event and fills ms[i] for i < min(cap, count) with the
+ * durations and names[i] with static kernel names; it returns the count. */
+int asj_timing_enable(int on);
+int asj_timing_read(float *ms, const char **names, int cap);
+
+/* Plain device-to-device copy of `bytes` bytes with the library's own
+ * kernel (used to calibrate hardware byte counters against a known size). */
+int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASJOIN_H */

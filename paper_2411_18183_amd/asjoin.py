@@ -1,0 +1,229 @@
+"""Python binding of libasjoin: the C entry points under the same names.
+
+Argument marshalling only -- every step of the join runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensors) and streams.  The
+library must have been built (``python -m paper_2411_18183_amd.build``);
+importing this module without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch  # loads the HIP runtime that libasjoin then shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasjoin.so")
+
+ASJ_OK = 0
+ASJ_EINVAL = -1
+ASJ_ENOMEM = -2
+ASJ_EOVERFLOW = -3
+ASJ_ETABLEFULL = -4
+ASJ_EHIP = -5
+ASJ_EUNSUPPORTED = -6
+
+ASJ_NO_VERIFY = 0x1
+ASJ_PLAIN = 0x2
+
+
+class AsjError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class asj_keys(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
+class asj_sig_params(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_int32), ("nsym", ctypes.c_int32)]
+
+
+class asj_opts(ctypes.Structure):
+    _fields_ = [("sig", asj_sig_params), ("load_factor", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libasjoin is not built ({LIB_PATH} missing); run python -m paper_2411_18183_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        L.asj_signature.argtypes = [ctypes.POINTER(asj_keys), asj_sig_params, P, P]
+        L.asj_build.argtypes = [ctypes.POINTER(asj_keys), ctypes.POINTER(asj_opts), ctypes.POINTER(P), P]
+        L.asj_probe.argtypes = [P, ctypes.POINTER(asj_keys), P, I64, P, P, P]
+        L.asj_join.argtypes = [ctypes.POINTER(asj_keys), ctypes.POINTER(asj_keys), ctypes.POINTER(asj_opts), P, I64,
+                               P, P, P]
+        L.asj_table_status.argtypes = [P]
+        L.asj_table_capacity.argtypes = [P]
+        L.asj_table_capacity.restype = I64
+        L.asj_table_free.argtypes = [P]
+        L.asj_strerror.argtypes = [ctypes.c_int]
+        L.asj_strerror.restype = ctypes.c_char_p
+        L.asj_timing_enable.argtypes = [ctypes.c_int]
+        L.asj_timing_read.argtypes = [P, P, ctypes.c_int]
+        L.asj_util_copy.argtypes = [P, P, I64, P]
+        for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_table_status", "asj_table_free",
+                     "asj_timing_enable", "asj_timing_read", "asj_util_copy"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().asj_strerror(code).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != ASJ_OK:
+        raise AsjError(rc, where)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class DeviceKeys:
+    """A relation's join attributes in device memory (see asj_keys)."""
+    data: torch.Tensor              # uint8
+    offsets: torch.Tensor           # int64, n + 1
+    ids: Optional[torch.Tensor]     # int32, n (None -> row index)
+
+    @property
+    def n(self) -> int:
+        return self.offsets.numel() - 1
+
+    @classmethod
+    def from_host(cls, rel, device="cuda", with_ids=True) -> "DeviceKeys":
+        """Copy a host relation (numpy data/offsets/ids) to the device."""
+        data = torch.from_numpy(rel.data).to(device)
+        off = torch.from_numpy(rel.offsets).to(device)
+        ids = torch.from_numpy(rel.ids).to(device) if (with_ids and rel.ids is not None) else None
+        return cls(data, off, ids)
+
+    def c(self) -> asj_keys:
+        for t, dt in ((self.data, torch.uint8), (self.offsets, torch.int64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("keys: data must be contiguous cuda uint8, offsets contiguous cuda int64")
+        if self.ids is not None and (self.ids.dtype != torch.int32 or not self.ids.is_cuda or
+                                     not self.ids.is_contiguous() or self.ids.numel() != self.n):
+            raise ValueError("keys: ids must be a contiguous cuda int32 tensor of n elements")
+        return asj_keys(self.data.data_ptr() if self.data.numel() else None, self.offsets.data_ptr(),
+                        self.ids.data_ptr() if self.ids is not None else None, self.n)
+
+
+def asj_signature(keys: DeviceKeys, f: int = 16, nsym: int = 2, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Signatures of every key (int32 tensor holding the uint32 bit patterns)."""
+    if out is None:
+        out = torch.empty(max(keys.n, 0), dtype=torch.int32, device=keys.offsets.device)
+    k = keys.c()
+    _check(lib().asj_signature(ctypes.byref(k), asj_sig_params(f, nsym),
+                               ctypes.c_void_p(out.data_ptr() if out.numel() else None), _stream(stream)),
+           "asj_signature")
+    return out
+
+
+class Table:
+    """asj_table handle; keeps the borrowed build relation alive."""
+
+    def __init__(self, handle: ctypes.c_void_p, keys: DeviceKeys):
+        self.handle = handle
+        self.keys = keys
+
+    @property
+    def capacity(self) -> int:
+        return int(lib().asj_table_capacity(self.handle))
+
+    def status(self) -> int:
+        return lib().asj_table_status(self.handle)
+
+    def free(self):
+        if self.handle:
+            _check(lib().asj_table_free(self.handle), "asj_table_free")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _opts(f, nsym, load_factor, flags) -> asj_opts:
+    return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags))
+
+
+def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.5, flags: int = 0,
+              stream=None) -> Table:
+    k = R.c()
+    o = _opts(f, nsym, load_factor, flags)
+    h = ctypes.c_void_p()
+    _check(lib().asj_build(ctypes.byref(k), ctypes.byref(o), ctypes.byref(h), _stream(stream)), "asj_build")
+    return Table(h, R)
+
+
+def asj_probe(t: Table, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, stream=None):
+    """Launch the probe.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
+    k = S.c()
+    cap = out.shape[0]
+    _check(lib().asj_probe(t.handle, ctypes.byref(k), ctypes.c_void_p(out.data_ptr() if cap else None), cap,
+                           ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(counts.data_ptr() + 8),
+                           _stream(stream)), "asj_probe")
+
+
+def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, f: int = 16, nsym: int = 2,
+             load_factor: float = 0.5, flags: int = 0, stream=None):
+    """Launch a whole join.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
+    kr, ks = R.c(), S.c()
+    o = _opts(f, nsym, load_factor, flags)
+    cap = out.shape[0]
+    _check(lib().asj_join(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
+                          ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.c_void_p(counts.data_ptr()),
+                          ctypes.c_void_p(counts.data_ptr() + 8), _stream(stream)), "asj_join")
+
+
+def join(R: DeviceKeys, S: DeviceKeys, cap: Optional[int] = None, **kw):
+    """Convenience two-call join: returns (pairs int32 [|T|, 2] on the device, |T|, candidates)."""
+    dev = S.offsets.device
+    if cap is None:
+        cap = max(1024, S.n)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    out = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    asj_join(R, S, out, counts, **kw)
+    total, ncand = (int(x) for x in counts.tolist())
+    if total > cap:
+        out = torch.empty((total, 2), dtype=torch.int32, device=dev)
+        asj_join(R, S, out, counts, **kw)
+        total, ncand = (int(x) for x in counts.tolist())
+    return out[:max(total, 0)], total, ncand
+
+
+def timing_enable(on: bool = True):
+    _check(lib().asj_timing_enable(1 if on else 0), "asj_timing_enable")
+
+
+def timing_read(cap: int = 16):
+    ms = (ctypes.c_float * cap)()
+    names = (ctypes.c_char_p * cap)()
+    n = lib().asj_timing_read(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(names, ctypes.c_void_p), cap)
+    if n < 0:
+        raise AsjError(n, "asj_timing_read")
+    return [(names[i].decode(), float(ms[i])) for i in range(min(n, cap))]
+
+
+def asj_util_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
+    _check(lib().asj_util_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes),
+                               _stream(stream)), "asj_util_copy")

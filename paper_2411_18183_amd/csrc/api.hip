@@ -1,0 +1,383 @@
+// Host side of the libasjoin C interface: argument checks, stream-ordered
+// allocation, kernel launches and error mapping.  Every step of the join
+// runs in the library's own kernels (sign.hip, table.hip, probe.hip).
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "asj_internal.h"
+
+struct asj_table {
+    asj_keys r;              // borrowed build relation
+    uint64_t *slots;         // capacity slots
+    int64_t capacity;        // power of two
+    int32_t *status;         // device word: 0 or ASJ_ETABLEFULL
+    int plain;               // baseline table (no signature stored)
+    int verify;              // probe compares key bytes of candidates
+    asj_sig_params sig;      // signature parameters of the build
+    hipStream_t stream;      // build stream (orders free)
+    int device;
+};
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr int kSignGridCap = 256 * 16;  // blocks; the sign kernel loops over windows
+constexpr int kProbeGridCap = 256 * 16;
+
+struct DeviceState {
+    uint16_t *tab = nullptr; // GF constant tables (device)
+    bool ready = false;
+};
+
+std::mutex g_mu;
+DeviceState g_dev[kMaxDevices];
+
+// ---- per-thread kernel timing (measurement support) ----
+constexpr int kMaxTimed = 16;
+struct Timing {
+    bool on = false;
+    int depth = 0;
+    int count = 0;
+    hipEvent_t ev[2 * kMaxTimed] = {};
+    const char *names[kMaxTimed] = {};
+};
+thread_local Timing g_tim;
+
+struct TimingScope { // resets the record at the outermost API call
+    TimingScope()
+    {
+        if (g_tim.depth++ == 0) g_tim.count = 0;
+    }
+    ~TimingScope() { g_tim.depth--; }
+};
+
+void tim_begin(const char *name, hipStream_t st)
+{
+    if (!g_tim.on || g_tim.count >= kMaxTimed) return;
+    int i = g_tim.count;
+    for (int e = 0; e < 2; e++)
+        if (!g_tim.ev[2 * i + e]) (void)hipEventCreate(&g_tim.ev[2 * i + e]);
+    g_tim.names[i] = name;
+    (void)hipEventRecord(g_tim.ev[2 * i], st);
+}
+
+void tim_end(hipStream_t st)
+{
+    if (!g_tim.on || g_tim.count >= kMaxTimed) return;
+    (void)hipEventRecord(g_tim.ev[2 * g_tim.count + 1], st);
+    g_tim.count++;
+}
+
+int hip_fail(hipError_t e)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return ASJ_ENOMEM;
+    return ASJ_EHIP;
+}
+
+#define TIMED(name, stmt)                      \
+    do {                                       \
+        tim_begin(name, st);                   \
+        hipError_t e_ = (stmt);                \
+        tim_end(st);                           \
+        if (e_ != hipSuccess) return hip_fail(e_); \
+    } while (0)
+
+int ensure_init(int *dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ASJ_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return ASJ_EHIP;
+    *dev_out = dev;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState &d = g_dev[dev];
+    if (d.ready) return ASJ_OK;
+    uint16_t *tab = nullptr;
+    if (hipMalloc((void **)&tab, sizeof(uint16_t) * ASJ_TAB_TOTAL_WORDS) != hipSuccess) return ASJ_ENOMEM;
+    if (asj_launch_tables(tab, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(tab);
+        return ASJ_EHIP;
+    }
+    // keep freed stream-ordered blocks cached in the default pool
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    d.tab = tab;
+    d.ready = true;
+    return ASJ_OK;
+}
+
+bool keys_ok(const asj_keys *k)
+{
+    if (!k || k->n < 0 || k->n >= (int64_t)INT32_MAX) return false;
+    if (k->n > 0 && !k->offsets) return false;
+    return true;
+}
+
+int resolve_sig(asj_sig_params p, asj_sig_params *out)
+{
+    if (p.f == 0 && p.nsym == 0) p = asj_sig_params{16, 2};
+    if (p.f == 16 && (p.nsym == 1 || p.nsym == 2)) {
+        *out = p;
+        return ASJ_OK;
+    }
+    if (p.f == 8 && (p.nsym == 2 || p.nsym == 4)) {
+        *out = p;
+        return ASJ_OK;
+    }
+    if (p.f != 8 && p.f != 16) return ASJ_EINVAL;
+    if (p.nsym < 1 || p.f * p.nsym > 32) return ASJ_EINVAL;
+    return ASJ_EUNSUPPORTED;
+}
+
+hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
+                           hipStream_t st)
+{
+    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st);
+    return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st);
+}
+
+template <typename T>
+hipError_t alloc_async(T **p, size_t count, hipStream_t st)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMallocAsync((void **)p, sizeof(T) * count, st);
+}
+
+int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t st)
+{
+    if (!table_out || !keys_ok(r)) return ASJ_EINVAL;
+    *table_out = nullptr;
+    asj_opts o = {};
+    if (opts) o = *opts;
+    const int plain = (o.flags & ASJ_PLAIN) != 0;
+    const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    if (plain && !verify) return ASJ_EINVAL; // the plain table has no signature to trust
+    asj_sig_params sig = {16, 2};
+    if (!plain) {
+        int rc = resolve_sig(o.sig, &sig);
+        if (rc != ASJ_OK) return rc;
+    }
+    float lf = o.load_factor > 0.0f ? o.load_factor : 0.5f;
+    if (!(lf > 0.0f && lf < 1.0f)) return ASJ_EINVAL;
+    int dev = 0;
+    int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+
+    int64_t cap = 64;
+    while ((double)cap * lf < (double)r->n) cap <<= 1;
+
+    asj_table *t = (asj_table *)calloc(1, sizeof(asj_table));
+    if (!t) return ASJ_ENOMEM;
+    t->r = *r;
+    t->capacity = cap;
+    t->plain = plain;
+    t->verify = verify;
+    t->sig = sig;
+    t->stream = st;
+    t->device = dev;
+    uint32_t *sig_r = nullptr;
+    hipError_t e = alloc_async(&t->slots, (size_t)cap, st);
+    if (e == hipSuccess) e = alloc_async(&t->status, 1, st);
+    if (e == hipSuccess) e = alloc_async(&sig_r, (size_t)r->n, st);
+    if (e != hipSuccess) {
+        if (t->slots) (void)hipFreeAsync(t->slots, st);
+        if (t->status) (void)hipFreeAsync(t->status, st);
+        if (sig_r) (void)hipFreeAsync(sig_r, st);
+        free(t);
+        return hip_fail(e);
+    }
+    int out_rc = ASJ_OK;
+    do {
+        hipError_t le;
+        tim_begin("table_init", st);
+        le = asj_launch_fill64(t->slots, cap, ASJ_EMPTY_SLOT, st);
+        if (le == hipSuccess) le = asj_launch_fill_i32(t->status, 1, 0, st);
+        tim_end(st);
+        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
+        tim_begin(plain ? "hash_build" : "sign_build", st);
+        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st);
+        tim_end(st);
+        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
+        tim_begin("insert", st);
+        le = asj_launch_insert(sig_r, r->n, plain, t->slots, (uint64_t)cap - 1, t->status, st);
+        tim_end(st);
+        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
+    } while (0);
+    (void)hipFreeAsync(sig_r, st);
+    if (out_rc != ASJ_OK) {
+        (void)hipFreeAsync(t->slots, st);
+        (void)hipFreeAsync(t->status, st);
+        free(t);
+        return out_rc;
+    }
+    *table_out = t;
+    return ASJ_OK;
+}
+
+int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
+               int64_t *cand_count, hipStream_t st)
+{
+    if (!t || !keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
+    int dev = 0;
+    int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    hipError_t e = asj_launch_fill_i64(out_count, 1, 0, st);
+    if (e == hipSuccess && cand_count) e = asj_launch_fill_i64(cand_count, 1, 0, st);
+    if (e != hipSuccess) return hip_fail(e);
+    uint32_t *sig_s = nullptr;
+    e = alloc_async(&sig_s, (size_t)s->n, st);
+    if (e != hipSuccess) return hip_fail(e);
+    int out_rc = ASJ_OK;
+    do {
+        hipError_t le;
+        tim_begin(t->plain ? "hash_probe_side" : "sign_probe_side", st);
+        le = launch_sign_for(s, t->sig, t->plain, sig_s, g_dev[dev].tab, st);
+        tim_end(st);
+        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
+        asj_probe_args a = {};
+        a.rdata = t->r.data;
+        a.roff = t->r.offsets;
+        a.rids = t->r.ids;
+        a.sdata = s->data;
+        a.soff = s->offsets;
+        a.sids = s->ids;
+        a.n = s->n;
+        a.sig_s = sig_s;
+        a.slots = t->slots;
+        a.mask = (uint64_t)t->capacity - 1;
+        a.out = out;
+        a.cap = out_cap;
+        a.out_count = out_count;
+        a.cand_count = cand_count;
+        a.table_status = t->status;
+        a.plain = t->plain;
+        a.verify = t->verify;
+        tim_begin("probe_verify", st);
+        le = asj_launch_probe(&a, kProbeGridCap, st);
+        tim_end(st);
+        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
+    } while (0);
+    (void)hipFreeAsync(sig_s, st);
+    return out_rc;
+}
+
+int table_free_impl(asj_table *t)
+{
+    if (!t) return ASJ_OK;
+    hipError_t e1 = hipFreeAsync(t->slots, t->stream);
+    hipError_t e2 = hipFreeAsync(t->status, t->stream);
+    free(t);
+    return (e1 == hipSuccess && e2 == hipSuccess) ? ASJ_OK : ASJ_EHIP;
+}
+
+} // namespace
+
+extern "C" {
+
+int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hipStream_t st)
+{
+    TimingScope ts;
+    if (!keys_ok(keys) || (keys->n > 0 && !sig_out)) return ASJ_EINVAL;
+    asj_sig_params sig;
+    int rc = resolve_sig(p, &sig);
+    if (rc != ASJ_OK) return rc;
+    int dev = 0;
+    rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st));
+    return ASJ_OK;
+}
+
+int asj_build(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t st)
+{
+    TimingScope ts;
+    return build_impl(r, opts, table_out, st);
+}
+
+int asj_probe(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
+              int64_t *cand_count, hipStream_t st)
+{
+    TimingScope ts;
+    return probe_impl(t, s, out, out_cap, out_count, cand_count, st);
+}
+
+int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+             int64_t *out_count, int64_t *cand_count, hipStream_t st)
+{
+    TimingScope ts;
+    if (!keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
+    asj_table *t = nullptr;
+    int rc = build_impl(r, opts, &t, st);
+    if (rc != ASJ_OK) return rc;
+    rc = probe_impl(t, s, out, out_cap, out_count, cand_count, st);
+    int rc2 = table_free_impl(t);
+    return rc != ASJ_OK ? rc : rc2;
+}
+
+int asj_table_status(const asj_table *t)
+{
+    if (!t) return ASJ_EINVAL;
+    if (hipStreamSynchronize(t->stream) != hipSuccess) return ASJ_EHIP;
+    int32_t v = 0;
+    if (hipMemcpy(&v, t->status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return ASJ_EHIP;
+    return v == 0 ? ASJ_OK : (int)v;
+}
+
+int64_t asj_table_capacity(const asj_table *t) { return t ? t->capacity : -1; }
+
+int asj_table_free(asj_table *t) { return table_free_impl(t); }
+
+const char *asj_strerror(int code)
+{
+    switch (code) {
+    case ASJ_OK: return "ok";
+    case ASJ_EINVAL: return "invalid argument";
+    case ASJ_ENOMEM: return "device allocation failed";
+    case ASJ_EOVERFLOW: return "result larger than the output capacity";
+    case ASJ_ETABLEFULL: return "hash table full";
+    case ASJ_EHIP: return "HIP runtime error";
+    case ASJ_EUNSUPPORTED: return "unsupported parameters";
+    default: return "unknown error";
+    }
+}
+
+int asj_timing_enable(int on)
+{
+    g_tim.on = on != 0;
+    g_tim.count = 0;
+    return ASJ_OK;
+}
+
+int asj_timing_read(float *ms, const char **names, int cap)
+{
+    const int n = g_tim.count;
+    if (n == 0) return 0;
+    if (hipEventSynchronize(g_tim.ev[2 * n - 1]) != hipSuccess) return ASJ_EHIP;
+    for (int i = 0; i < n && i < cap; i++) {
+        float v = 0.0f;
+        if (hipEventElapsedTime(&v, g_tim.ev[2 * i], g_tim.ev[2 * i + 1]) != hipSuccess) return ASJ_EHIP;
+        if (ms) ms[i] = v;
+        if (names) names[i] = g_tim.names[i];
+    }
+    return n;
+}
+
+int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
+{
+    if (bytes < 0 || (bytes > 0 && (!dst || !src))) return ASJ_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) & 15u) return ASJ_EINVAL;
+    int dev = 0;
+    int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    TimingScope ts;
+    TIMED("copy", asj_launch_copy(dst, src, bytes, st));
+    return ASJ_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP translation units of libasjoin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/asjoin.h"
+
+#define ASJ_WAVE 64
+#define ASJ_CHUNK 64          // key bytes handled by one lane per pass
+#define ASJ_EMPTY_SLOT (~0ull)
+
+// ---------------------------------------------------------------------------
+// GF(2^16) constant-multiply tables.
+//
+// Multiplying a 16-bit field element v by a fixed constant c is linear over
+// GF(2), so it is the XOR of two byte-indexed lookups:
+//     v * c = T_c[v & 255] ^ T_c[256 + (v >> 8)],
+// with T_c[b] = b * c and T_c[256 + b] = (b x^8) * c.  Each table pair is
+// 512 uint16 = 1 KB.  The library builds the pairs it needs once per device
+// (field polynomial x^16 + x^12 + x^3 + x + 1, alpha = x).
+//
+// Index map (ASJ_NTAB16 pairs), components j = 1, 2:
+//   0                     c = x^16 (folds bits 16..31 of an unreduced word)
+//   1 + 17(j-1) + v       c = alpha^(32 j v),   v = 0..7  (chunk index digit 0)
+//   1 + 17(j-1) + 8 + v   c = alpha^(256 j v),  v = 0..7  (chunk index digit 1)
+//   1 + 17(j-1) + 16      c = alpha^(2048 j)             (64-chunk block)
+// ---------------------------------------------------------------------------
+#define ASJ_TAB_WORDS 512
+#define ASJ_NTAB16 35
+#define ASJ_TAB_RED 0
+__host__ __device__ inline int asj_tab_d0(int j, int v) { return 1 + 17 * (j - 1) + v; }
+__host__ __device__ inline int asj_tab_d1(int j, int v) { return 1 + 17 * (j - 1) + 8 + v; }
+__host__ __device__ inline int asj_tab_blk(int j) { return 1 + 17 * (j - 1) + 16; }
+
+// GF(2^8) (polynomial x^8 + x^4 + x^3 + x^2 + 1, alpha = x) tables, stored
+// after the GF(2^16) pairs as uint16 words (low byte used):
+//   [0, 510)       exp8[e] = alpha^(e mod 255)
+//   [512, 768)     log8[v]  (log8[0] unused)
+//   [768 + 256(k-1) + b]   b * x^(8k) mod g8, k = 1, 2, 3 (fold bytes 1..3)
+#define ASJ_NTAB8 4
+#define ASJ_TAB8_BASE (ASJ_NTAB16 * ASJ_TAB_WORDS)
+#define ASJ_TAB8_EXP 0
+#define ASJ_TAB8_LOG 512
+#define ASJ_TAB8_RED 768
+#define ASJ_TAB_TOTAL_WORDS ((ASJ_NTAB16 + ASJ_NTAB8) * ASJ_TAB_WORDS)
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+typedef uint32_t asj_u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ inline void asj_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bijective 32-bit mixer (finalizer of MurmurHash3) used to place a
+// signature in the table; any bijection gives the same join output.
+__host__ __device__ inline uint32_t asj_mix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ inline uint32_t asj_cmul16(uint32_t v, const uint16_t *t)
+{
+    return (uint32_t)t[v & 255u] ^ (uint32_t)t[256u + (v >> 8)];
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ inline int asj_wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & (ASJ_WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < ASJ_WAVE; d <<= 1) {
+        int o = __shfl_up(v, d, ASJ_WAVE);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Load key bytes [k0, k0 + 64) of a key stored at arena bytes [s, s + len)
+// into 16 little-endian words (word t = key bytes k0+4t .. k0+4t+3).  Key
+// bytes at or past len read as zero.  Only 4-byte-aligned words that hold at
+// least one byte of the key are read, so the load never leaves the pages of
+// the arena.  Requires 0 <= k0 < len.
+__device__ inline void asj_load_chunk(const uint8_t *__restrict__ data, int64_t s, int64_t len, int64_t k0,
+                                      uint32_t kd[16])
+{
+    const int64_t a = s + k0;
+    const int sh = (int)(a & 3);
+    const uint32_t *p = (const uint32_t *)(data + (a - sh));
+    const int64_t avail = (s + len) - (a - sh); // readable bytes starting at p
+    uint32_t d[17];
+    if (avail >= (sh ? 68 : 64)) {
+        const asj_u32x4 *q = (const asj_u32x4 *)p;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            asj_u32x4 v = q[t];
+            d[4 * t + 0] = v.x;
+            d[4 * t + 1] = v.y;
+            d[4 * t + 2] = v.z;
+            d[4 * t + 3] = v.w;
+        }
+        d[16] = sh ? p[16] : 0u;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 17; t++) d[t] = (4 * t < avail) ? p[t] : 0u;
+    }
+    if (sh) {
+#pragma unroll
+        for (int t = 0; t < 16; t++) kd[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], (uint32_t)sh);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 16; t++) kd[t] = d[t];
+    }
+    const int64_t rem = len - k0;
+    if (rem < 64) {
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int64_t nb = rem - 4 * t;
+            uint32_t m = nb >= 4 ? 0xFFFFFFFFu : (nb <= 0 ? 0u : ((1u << (8 * (int)nb)) - 1u));
+            kd[t] &= m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files; all asynchronous on `st`)
+// ---------------------------------------------------------------------------
+enum asj_sign_mode {
+    ASJ_MODE_SIG16 = 0, // GF(2^16) signature, nsym components (1 or 2)
+    ASJ_MODE_SIG8 = 1,  // GF(2^8) signature, nsym components (2 or 4)
+    ASJ_MODE_PLAIN = 2, // plain multiplicative full-key hash (baseline)
+};
+
+hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
+hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
+                           int grid_cap, hipStream_t st);
+hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
+hipError_t asj_launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
+hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
+                             int32_t *status, hipStream_t st);
+
+struct asj_probe_args {
+    const uint8_t *rdata;
+    const int64_t *roff;
+    const int32_t *rids;
+    const uint8_t *sdata;
+    const int64_t *soff;
+    const int32_t *sids;
+    int64_t n;
+    const uint32_t *sig_s;
+    const uint64_t *slots;
+    uint64_t mask;
+    asj_pair *out;
+    int64_t cap;
+    int64_t *out_count;
+    int64_t *cand_count;
+    const int32_t *table_status; // device; non-zero means the build failed
+    int plain;
+    int verify;
+};
+hipError_t asj_launch_probe(const asj_probe_args *a, int grid_cap, hipStream_t st);
+hipError_t asj_launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);

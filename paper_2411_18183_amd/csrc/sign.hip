@@ -1,0 +1,216 @@
+// Signature of every key (Section 3.1), and the plain full-key hash of the
+// baseline simple hash join (Section 2), on gfx950.
+//
+// Work decomposition.  A key of len bytes is cut into ceil(len / 64)
+// key-relative chunks of 64 bytes.  A wave takes a window of 64 consecutive
+// keys, lays all their chunks out back to back and processes them in passes
+// of 64 chunks, one chunk per lane, so that short and long keys (16 B ..
+// 10 KB and beyond) keep every lane busy.  A lane reads its chunk with
+// 16-byte loads, realigns it to key-relative words, folds it into a partial
+// signature, scales the partial to the chunk's position in the key and
+// XORs it (GF addition) into the key's accumulator in LDS.
+//
+// Chunk arithmetic (GF(2^16), components j = 1, 2).  Component j of a chunk
+// is sum_u p_u alpha^(j u) over its 32 symbols.  Instead of one log/antilog
+// multiplication per symbol, the lane runs Horner's rule over groups of 8
+// symbols with an unreduced accumulator: shifting by one bit is
+// multiplication by alpha = x, so a group costs shifts and XORs only, and
+// the bits that overflow 16 are folded back with one or two byte-indexed
+// table lookups (T[b] = b x^16).  Scaling a chunk to its position multiplies
+// by alpha^(32 j c) for chunk index c, done digit by digit with constant
+// tables (c = d0 + 8 d1 + 64 blk).
+#include "asj_internal.h"
+
+namespace {
+
+constexpr int kBlock = 512;
+constexpr int kWaves = kBlock / ASJ_WAVE;
+
+__device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
+
+// GF(2^16): both components of one 64-byte chunk, positions relative to the
+// chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
+template <int NSYM>
+__device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
+{
+    const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
+    uint32_t a1 = 0, a2 = 0;
+#pragma unroll
+    for (int q = 3; q >= 0; q--) {
+        const uint32_t w0 = kd[4 * q], w1 = kd[4 * q + 1], w2 = kd[4 * q + 2], w3 = kd[4 * q + 3];
+        // component 1: symbols p_v (v = 0..7 of the group) shifted by v
+        const uint32_t u1 = lo16(w0) ^ (hi16(w0) << 1) ^ (lo16(w1) << 2) ^ (hi16(w1) << 3) ^ (lo16(w2) << 4) ^
+                            (hi16(w2) << 5) ^ (lo16(w3) << 6) ^ (hi16(w3) << 7);
+        const uint32_t t1 = (a1 << 8) ^ u1; // < 2^24
+        a1 = (t1 & 0xFFFFu) ^ red[t1 >> 16];
+        if (NSYM == 2) {
+            // component 2: p_v shifted by 2v
+            const uint32_t u2 = lo16(w0) ^ (hi16(w0) << 2) ^ (lo16(w1) << 4) ^ (hi16(w1) << 6) ^ (lo16(w2) << 8) ^
+                                (hi16(w2) << 10) ^ (lo16(w3) << 12) ^ (hi16(w3) << 14);
+            const uint32_t t2 = (a2 << 16) ^ u2; // < 2^32
+            a2 = (t2 & 0xFFFFu) ^ asj_cmul16(t2 >> 16, red);
+        }
+    }
+    // position of the chunk in the key: multiply by alpha^(32 j c)
+    const int d0 = c & 7, d1 = (c >> 3) & 7;
+    a1 = asj_cmul16(a1, tab + asj_tab_d0(1, d0) * ASJ_TAB_WORDS);
+    a1 = asj_cmul16(a1, tab + asj_tab_d1(1, d1) * ASJ_TAB_WORDS);
+    if (NSYM == 2) {
+        a2 = asj_cmul16(a2, tab + asj_tab_d0(2, d0) * ASJ_TAB_WORDS);
+        a2 = asj_cmul16(a2, tab + asj_tab_d1(2, d1) * ASJ_TAB_WORDS);
+    }
+    for (int blk = c >> 6; blk > 0; blk--) {
+        a1 = asj_cmul16(a1, tab + asj_tab_blk(1) * ASJ_TAB_WORDS);
+        if (NSYM == 2) a2 = asj_cmul16(a2, tab + asj_tab_blk(2) * ASJ_TAB_WORDS);
+    }
+    return a1 | (a2 << 16);
+}
+
+// GF(2^8): byte symbols, NSYM components of 8 bits; component j of the chunk
+// is sum_u b_u alpha^(j u), u = 0..63, then scaled by alpha^(64 j c).
+template <int NSYM>
+__device__ __forceinline__ uint32_t chunk_sig8(const uint32_t kd[16], const uint16_t *__restrict__ t8, int c)
+{
+    const uint16_t *ex = t8 + ASJ_TAB8_EXP, *lg = t8 + ASJ_TAB8_LOG, *red = t8 + ASJ_TAB8_RED;
+    uint32_t acc[NSYM];
+#pragma unroll
+    for (int j = 0; j < NSYM; j++) acc[j] = 0;
+#pragma unroll
+    for (int t = 15; t >= 0; t--) {
+        const uint32_t w = kd[t];
+        const uint32_t b0 = w & 255u, b1 = (w >> 8) & 255u, b2 = (w >> 16) & 255u, b3 = w >> 24;
+#pragma unroll
+        for (int j = 1; j <= NSYM; j++) {
+            // four symbols per word: Horner step by alpha^(4j), unreduced
+            const uint32_t u = b0 ^ (b1 << j) ^ (b2 << (2 * j)) ^ (b3 << (3 * j));
+            const uint32_t T = (acc[j - 1] << (4 * j)) ^ u; // < 2^(8 + 4j) <= 2^24
+            uint32_t v = (T & 255u) ^ red[(T >> 8) & 255u];
+            if (j > 2) v ^= red[256 + ((T >> 16) & 255u)];
+            acc[j - 1] = v;
+        }
+    }
+    uint32_t out = 0;
+#pragma unroll
+    for (int j = 1; j <= NSYM; j++) {
+        uint32_t v = acc[j - 1];
+        if (v) v = ex[(lg[v] + (uint32_t)((64ull * j * (uint64_t)c) % 255u)) % 255u];
+        out |= v << (8 * (j - 1));
+    }
+    return out;
+}
+
+// Plain multiplicative hash of one chunk, seeded by its index (baseline).
+__device__ __forceinline__ uint32_t chunk_plain(const uint32_t kd[16], int c)
+{
+    uint32_t h = 0x9E3779B9u * (uint32_t)(c + 1);
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        h = (h ^ kd[t]) * 0x85EBCA77u;
+        h ^= h >> 15;
+    }
+    return h;
+}
+
+template <int MODE, int NSYM>
+__global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
+                                                      const int64_t *__restrict__ off, int64_t n,
+                                                      uint32_t *__restrict__ out, const uint16_t *__restrict__ gtab)
+{
+    constexpr int kTabWords = MODE == ASJ_MODE_SIG16 ? ASJ_NTAB16 * ASJ_TAB_WORDS
+                              : MODE == ASJ_MODE_SIG8 ? ASJ_NTAB8 * ASJ_TAB_WORDS
+                                                      : 2;
+    __shared__ uint16_t tab[kTabWords];
+    __shared__ int64_t kst[kWaves][ASJ_WAVE];
+    __shared__ int32_t klen[kWaves][ASJ_WAVE];
+    __shared__ int32_t kin[kWaves][ASJ_WAVE]; // inclusive prefix of chunk counts
+    __shared__ uint32_t kacc[kWaves][ASJ_WAVE];
+
+    if (MODE != ASJ_MODE_PLAIN) {
+        const uint16_t *src = gtab + (MODE == ASJ_MODE_SIG8 ? ASJ_TAB8_BASE : 0);
+        for (int i = threadIdx.x; i < kTabWords / 2; i += kBlock)
+            reinterpret_cast<uint32_t *>(tab)[i] = reinterpret_cast<const uint32_t *>(src)[i];
+        __syncthreads();
+    }
+
+    const int wave = threadIdx.x / ASJ_WAVE;
+    const int lane = threadIdx.x % ASJ_WAVE;
+    int64_t *wst = kst[wave];
+    int32_t *wlen = klen[wave];
+    int32_t *win_ = kin[wave];
+    uint32_t *wacc = kacc[wave];
+
+    const int64_t nwin = (n + ASJ_WAVE - 1) / ASJ_WAVE;
+    for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
+        const int64_t k = w * ASJ_WAVE + lane;
+        int64_t s = 0;
+        int32_t len = 0;
+        if (k < n) {
+            s = off[k];
+            len = (int32_t)(off[k + 1] - s);
+        }
+        const int nch = (len + ASJ_CHUNK - 1) / ASJ_CHUNK;
+        const int incl = asj_wave_incl_scan(nch);
+        const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
+        wst[lane] = s;
+        wlen[lane] = len;
+        win_[lane] = incl;
+        wacc[lane] = 0;
+        asj_wave_sync();
+        for (int base = 0; base < total; base += ASJ_WAVE) {
+            const int x = base + lane;
+            if (x < total) {
+                int lo = 0, hi = ASJ_WAVE - 1; // smallest i with incl[i] > x
+#pragma unroll
+                for (int it = 0; it < 6; it++) {
+                    const int mid = (lo + hi) >> 1;
+                    if (win_[mid] > x) hi = mid;
+                    else lo = mid + 1;
+                }
+                const int i = lo;
+                const int32_t li = wlen[i];
+                const int c = x - (win_[i] - (li + ASJ_CHUNK - 1) / ASJ_CHUNK);
+                uint32_t kd[16];
+                asj_load_chunk(data, wst[i], li, (int64_t)c * ASJ_CHUNK, kd);
+                uint32_t v;
+                if (MODE == ASJ_MODE_SIG16) v = chunk_sig16<NSYM>(kd, tab, c);
+                else if (MODE == ASJ_MODE_SIG8) v = chunk_sig8<NSYM>(kd, tab, c);
+                else v = chunk_plain(kd, c);
+                atomicXor(&wacc[i], v);
+            }
+        }
+        asj_wave_sync();
+        if (k < n) {
+            uint32_t v = wacc[lane];
+            if (MODE == ASJ_MODE_PLAIN) v = asj_mix32(v ^ ((uint32_t)len * 0xC2B2AE3Du));
+            out[k] = v;
+        }
+        asj_wave_sync();
+    }
+}
+
+template <int MODE, int NSYM>
+hipError_t launch(const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap, hipStream_t st)
+{
+    const int64_t nwin = (k->n + ASJ_WAVE - 1) / ASJ_WAVE;
+    int64_t blocks = (nwin + kWaves - 1) / kWaves;
+    if (blocks > grid_cap) blocks = grid_cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((sign_kernel<MODE, NSYM>), dim3((unsigned)blocks), dim3(kBlock), 0, st, k->data, k->offsets,
+                       k->n, out, tab);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap,
+                           hipStream_t st)
+{
+    if (k->n == 0) return hipSuccess;
+    if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch<ASJ_MODE_SIG16, 2>(k, out, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch<ASJ_MODE_SIG16, 1>(k, out, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch<ASJ_MODE_SIG8, 4>(k, out, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 2) return launch<ASJ_MODE_SIG8, 2>(k, out, tab, grid_cap, st);
+    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, tab, grid_cap, st);
+    return hipErrorInvalidValue;
+}

@@ -1,0 +1,98 @@
+// Build(R, H_sign) (Section 3.2, Figure 2): every build row's signature is
+// placed in an open-addressing table of 64-bit slots
+//     slot = signature << 32 | row        (empty slot = all ones),
+// at mix32(signature) modulo the power-of-two capacity, moving to the next
+// slot while the CAS finds it taken (linear probing).  Rows with equal
+// signatures are all kept (a multimap): they share a home slot, so every
+// one of them lies on the run a probe walks until the first empty slot.
+//
+// The baseline simple hash join (Section 2) uses the same layout with the
+// plain key hash choosing the home slot and no signature stored (the high
+// word is zero), so its probe must compare every occupied slot it visits.
+#include "asj_internal.h"
+
+namespace {
+
+__global__ void fill64_kernel(uint64_t *__restrict__ p, int64_t n, uint64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <int PLAIN>
+__global__ void insert_kernel(const uint32_t *__restrict__ sig, int64_t m, uint64_t *__restrict__ slots,
+                              uint64_t mask, int32_t *__restrict__ status)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t sg = sig[r];
+        const uint64_t val = PLAIN ? (uint64_t)(uint32_t)r : (((uint64_t)sg << 32) | (uint32_t)r);
+        uint64_t h = asj_mix32(sg) & mask;
+        uint64_t tries = 0;
+        for (;;) {
+            const uint64_t old = atomicCAS((unsigned long long *)&slots[h], (unsigned long long)ASJ_EMPTY_SLOT,
+                                           (unsigned long long)val);
+            if (old == ASJ_EMPTY_SLOT) break;
+            h = (h + 1) & mask;
+            if (++tries > mask) { // every slot taken
+                atomicExch(status, (int32_t)ASJ_ETABLEFULL);
+                break;
+            }
+        }
+    }
+}
+
+int grid_for(int64_t n, int block, int cap)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+} // namespace
+
+hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill64_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
+                             int32_t *status, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    if (plain)
+        hipLaunchKernelGGL(insert_kernel<1>, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, sig, m, slots, mask,
+                           status);
+    else
+        hipLaunchKernelGGL(insert_kernel<0>, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, sig, m, slots, mask,
+                           status);
+    return hipGetLastError();
+}

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path against the oracle, through the C interface.
+
+Signatures must be bit-exact (integer work); join outputs must be equal as
+multisets of (r_id, s_id) pairs (compared sorted; several orders are
+correct); candidate counts must equal the oracle's signature-equal pair
+count exactly.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_18183_amd import asjoin as A
+    A.lib()
+    return A
+
+
+def gpu_sigs(A, rel, f=16, nsym=2):
+    keys = A.DeviceKeys.from_host(rel)
+    out = A.asj_signature(keys, f, nsym)
+    return out.cpu().numpy().view(np.uint32).astype(np.uint64)
+
+
+def gpu_join(A, R, S, **kw):
+    Rk, Sk = A.DeviceKeys.from_host(R), A.DeviceKeys.from_host(S)
+    pairs, total, ncand = A.join(Rk, Sk, **kw)
+    return pairs.cpu().numpy(), total, ncand
+
+
+def adversarial_keys(rng):
+    lens = (list(range(0, 140)) + [255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2049, 4095, 4096, 4097,
+                                   4159, 4160, 4161, 8191, 8192, 8193, 10000, 12345, 65536, 131067, 131068, 131072])
+    keys = []
+    for i, L in enumerate(lens):
+        kind = i % 4
+        if kind == 0:
+            keys.append(rng.integers(0, 256, size=L, dtype=np.uint8).tobytes())
+        elif kind == 1:
+            keys.append(b"\xff" * L)
+        elif kind == 2:
+            keys.append(bytes(L))
+        else:
+            keys.append(rng.integers(0x20, 0x7F, size=L, dtype=np.uint8).tobytes())
+    return keys
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2, 3, 5, 15, 16])
+@pytest.mark.parametrize("params", [(16, 2), (16, 1), (8, 4), (8, 2)])
+def test_signature_bitexact_adversarial(A, oracle, wl, shift, params):
+    rng = np.random.default_rng(100 + shift)
+    rel = wl.unaligned_copy(wl.from_keys(adversarial_keys(rng)), shift)
+    f, nsym = params
+    assert np.array_equal(gpu_sigs(A, rel, f, nsym), oracle.signatures(rel, f, nsym))
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", 1.0), ("large", 0.01), ("dna", 0.004)])
+def test_signature_bitexact_workloads(A, oracle, wl, name, scale):
+    w = getattr(wl, name)(scale=scale)
+    for rel in (w.R, w.S):
+        assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
+
+
+def test_signature_bitexact_batch_keys(A, oracle, wl):
+    b = wl.batch(scale=0.002, njoins=16)
+    assert np.array_equal(gpu_sigs(A, b.S), oracle.signatures(b.S))
+
+
+def test_signature_many_windows_and_ragged_tail(A, oracle, wl):
+    # 64-key windows with every chunk count from 0 to ~70 and a ragged last window
+    rng = np.random.default_rng(7)
+    lens = rng.integers(0, 4500, size=64 * 37 + 13)
+    lens[::5] = rng.integers(0, 65, size=len(lens[::5]))
+    keys = [rng.integers(0, 256, size=int(L), dtype=np.uint8).tobytes() for L in lens]
+    rel = wl.from_keys(keys)
+    assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_join_small_random(A, oracle, wl, seed):
+    alphabets = [b"ab\x00", b"a", b"\x00", bytes(range(256)), b"xy"]
+    w = wl.random_small(seed, m=int(50 + 37 * seed), n=int(70 + 53 * seed), max_len=[1, 3, 9, 40, 300][seed % 5],
+                        alphabet=alphabets[seed % 5])
+    if seed % 2:
+        w.R.ids = (np.random.default_rng(seed).permutation(w.R.n) + 1000).astype(np.int32)
+        w.S.ids = (np.random.default_rng(seed + 1).permutation(w.S.n) + 7000).astype(np.int32)
+    want = oracle.join_nested(w.R, w.S)
+    _, want_cand = oracle.join_signature(w.R, w.S)
+    got, total, ncand = gpu_join(A, w.R, w.S)
+    assert total == len(want)
+    assert np.array_equal(oracle.sort_pairs(got), want)
+    assert ncand == want_cand
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", 1.0), ("large", 0.02), ("dna", 0.01)])
+def test_join_workloads(A, oracle, wl, name, scale):
+    w = getattr(wl, name)(scale=scale)
+    want, want_cand = oracle.join_signature(w.R, w.S)
+    got, total, ncand = gpu_join(A, w.R, w.S)
+    assert total == len(want) == w.meta["expected_matches"]
+    assert np.array_equal(oracle.sort_pairs(got), want)
+    assert ncand == want_cand
+
+
+def test_join_batch_members(A, oracle, wl):
+    b = wl.batch(scale=0.003, njoins=10)
+    for k in range(b.njoins):
+        j = b.join(k)
+        want, want_cand = oracle.join_signature(j.R, j.S)
+        got, total, ncand = gpu_join(A, j.R, j.S)
+        assert total == len(want)
+        assert np.array_equal(oracle.sort_pairs(got), want)
+        assert ncand == want_cand
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plain_baseline_join(A, oracle, wl, seed):
+    w = wl.random_small(seed, m=300, n=500, max_len=[2, 9, 80, 700][seed], alphabet=b"ab\x00")
+    got, total, _ = gpu_join(A, w.R, w.S, flags=A.ASJ_PLAIN)
+    want = oracle.join_nested(w.R, w.S)
+    assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)
+    t = wl.tiny(scale=0.5)
+    got, total, _ = gpu_join(A, t.R, t.S, flags=A.ASJ_PLAIN)
+    assert np.array_equal(oracle.sort_pairs(got), oracle.join_hash(t.R, t.S))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_paper_literal_no_verify(A, oracle, wl, seed):
+    w = wl.random_small(seed, m=200, n=300, max_len=[2, 6, 30, 3][seed], alphabet=b"a\x00")
+    want, want_cand = oracle.join_signature(w.R, w.S, verify=False)
+    got, total, ncand = gpu_join(A, w.R, w.S, flags=A.ASJ_NO_VERIFY)
+    assert total == len(want) == ncand == want_cand
+    assert np.array_equal(oracle.sort_pairs(got), want)
+
+
+def test_variant_signature_joins(A, oracle, wl):
+    w = wl.random_small(3, m=400, n=600, max_len=50, alphabet=b"ab\x00")
+    for f, nsym in ((16, 1), (8, 4), (8, 2)):
+        want, want_cand = oracle.join_signature(w.R, w.S, f=f, nsym=nsym)
+        got, total, ncand = gpu_join(A, w.R, w.S, f=f, nsym=nsym)
+        assert np.array_equal(oracle.sort_pairs(got), want)
+        assert ncand == want_cand
+
+
+def test_duplicate_keys_multimap(A, oracle, wl):
+    keys_r = [b"k" * 100] * 150 + [b"x" * 7] * 3 + [b""] * 4 + [bytes([i % 7]) * (i % 300) for i in range(500)]
+    keys_s = [b"k" * 100] * 40 + [b""] * 5 + [b"x" * 7] + [bytes([i % 5]) * (i % 200) for i in range(700)]
+    R, S = wl.from_keys(keys_r), wl.from_keys(keys_s)
+    want = oracle.join_hash(R, S)
+    got, total, _ = gpu_join(A, R, S, cap=10)  # forces the second call
+    assert total == len(want) >= 150 * 40
+    assert np.array_equal(oracle.sort_pairs(got), want)
+
+
+def test_overflow_reports_full_count(A, oracle, wl):
+    import torch
+    w = wl.tiny(scale=0.3)
+    Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+    want = oracle.join_hash(w.R, w.S)
+    cap = len(want) // 3
+    out = torch.full((cap, 2), -1, dtype=torch.int32, device="cuda")
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    A.asj_join(Rk, Sk, out, counts)
+    assert int(counts[0]) == len(want)
+    part = {tuple(p) for p in out.cpu().numpy().tolist()}
+    assert len(part) == cap and part <= {tuple(p) for p in want.tolist()}
+
+
+def test_empty_relations(A, oracle, wl):
+    empty = wl.from_keys([])
+    some = wl.from_keys([b"a", b"", b"bb"])
+    for R, S in ((empty, some), (some, empty), (empty, empty)):
+        got, total, ncand = gpu_join(A, R, S)
+        assert total == 0 and len(got) == 0 and ncand == 0
+    allempty = wl.from_keys([b""] * 5)
+    got, total, _ = gpu_join(A, allempty, wl.from_keys([b""] * 3))
+    assert total == 15
+
+
+def test_build_once_probe_twice_on_two_streams(A, oracle, wl):
+    import torch
+    w = wl.large(scale=0.005)
+    Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+    t = A.asj_build(Rk)
+    assert t.status() == A.ASJ_OK
+    cap = t.capacity
+    assert cap & (cap - 1) == 0 and cap >= 2 * w.R.n
+    want = oracle.join_hash(w.R, w.S)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for st in (s1, s2):
+        out = torch.empty((len(want) + 10, 2), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        A.asj_probe(t, Sk, out, cnt, stream=st)
+        outs.append((out, cnt))
+    torch.cuda.synchronize()
+    for out, cnt in outs:
+        n = int(cnt[0])
+        assert n == len(want)
+        assert np.array_equal(oracle.sort_pairs(out[:n].cpu().numpy()), want)
+    t.free()
+
+
+def test_rejects_bad_parameters(A, wl):
+    rel = A.DeviceKeys.from_host(wl.from_keys([b"abc"]))
+    with pytest.raises(A.AsjError) as e:
+        A.asj_signature(rel, 8, 3)  # valid width, no kernel for it
+    assert e.value.code == A.ASJ_EUNSUPPORTED
+    with pytest.raises(A.AsjError) as e:
+        A.asj_signature(rel, 16, 3)  # 48 bits do not fit the 32-bit signature word
+    assert e.value.code == A.ASJ_EINVAL
+    with pytest.raises(A.AsjError) as e:
+        A.asj_signature(rel, 12, 2)
+    assert e.value.code == A.ASJ_EINVAL
+    with pytest.raises(A.AsjError):
+        A.asj_build(rel, load_factor=1.5)
+    with pytest.raises(A.AsjError):
+        A.asj_build(rel, flags=A.ASJ_PLAIN | A.ASJ_NO_VERIFY)
