@@ -154,11 +154,13 @@ const char *asj_strerror(int code);
 
 /* ---- measurement support (not part of the join) ---- */
 
-/* Per-kernel timing of the last asj_join()/asj_build()/asj_probe() issued
- * by this thread while timing is on: HIP events are recorded around each
- * kernel on the call's stream.  asj_timing_read() synchronizes with the
- * last recorded event and fills ms[i] for i < min(cap, count) with the
- * durations and names[i] with static kernel names; it returns the count. */
+/* Per-kernel timing.  While enabled, every kernel phase that this thread
+ * launches through the library is bracketed by two HIP events recorded on
+ * the call's stream; up to 4096 records accumulate.  asj_timing_read()
+ * waits for the last recorded event, fills ms[i] (milliseconds) and
+ * names[i] (static phase names) for i < min(cap, count), clears the record
+ * and returns the count (or a negative error).  asj_timing_enable() clears
+ * the record as well. */
 int asj_timing_enable(int on);
 int asj_timing_read(float *ms, const char **names, int cap);
 

@@ -36,22 +36,20 @@ std::mutex g_mu;
 DeviceState g_dev[kMaxDevices];
 
 // ---- per-thread kernel timing (measurement support) ----
-constexpr int kMaxTimed = 16;
+// While timing is on, every kernel phase launched by this thread is
+// bracketed by two events on its stream; records accumulate until
+// asj_timing_read() collects them.
+constexpr int kMaxTimed = 4096;
 struct Timing {
     bool on = false;
-    int depth = 0;
     int count = 0;
     hipEvent_t ev[2 * kMaxTimed] = {};
     const char *names[kMaxTimed] = {};
 };
 thread_local Timing g_tim;
 
-struct TimingScope { // resets the record at the outermost API call
-    TimingScope()
-    {
-        if (g_tim.depth++ == 0) g_tim.count = 0;
-    }
-    ~TimingScope() { g_tim.depth--; }
+struct TimingScope { // kept for call-site symmetry; records are never reset here
+    TimingScope() {}
 };
 
 void tim_begin(const char *name, hipStream_t st)
@@ -365,6 +363,7 @@ int asj_timing_read(float *ms, const char **names, int cap)
         if (ms) ms[i] = v;
         if (names) names[i] = g_tim.names[i];
     }
+    g_tim.count = 0;
     return n;
 }
 

@@ -86,50 +86,66 @@ __device__ inline int asj_wave_incl_scan(int v)
     return v;
 }
 
-// Load key bytes [k0, k0 + 64) of a key stored at arena bytes [s, s + len)
-// into 16 little-endian words (word t = key bytes k0+4t .. k0+4t+3).  Key
-// bytes at or past len read as zero.  Only 4-byte-aligned words that hold at
-// least one byte of the key are read, so the load never leaves the pages of
-// the arena.  Requires 0 <= k0 < len.
-__device__ inline void asj_load_chunk(const uint8_t *__restrict__ data, int64_t s, int64_t len, int64_t k0,
-                                      uint32_t kd[16])
+// Chunk loaders.  A key of len bytes is read as floor(len / 64) full 64-byte
+// chunks and, when len is not a multiple of 64, one tail chunk of len % 64
+// bytes.  Both return 16 little-endian words holding key-relative bytes
+// (word t = key bytes k0+4t .. k0+4t+3, where `a` is the arena address of
+// key byte k0).  Only 4-byte-aligned words that hold at least one byte of
+// the key are read, so a load never leaves the pages of the arena.
+
+// Full chunk: the 64 bytes at a are all key bytes.  Words are read at
+// a & ~3 and realigned; the 17th word (needed when a is not 4-aligned)
+// still starts before the key's end.
+__device__ __forceinline__ void asj_load_full(const uint8_t *__restrict__ data, int64_t a, uint32_t kd[16])
 {
-    const int64_t a = s + k0;
-    const int sh = (int)(a & 3);
+    const uint32_t sh = (uint32_t)(a & 3);
     const uint32_t *p = (const uint32_t *)(data + (a - sh));
-    const int64_t avail = (s + len) - (a - sh); // readable bytes starting at p
+    const asj_u32x4 *q = (const asj_u32x4 *)p;
     uint32_t d[17];
-    if (avail >= (sh ? 68 : 64)) {
-        const asj_u32x4 *q = (const asj_u32x4 *)p;
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-            asj_u32x4 v = q[t];
-            d[4 * t + 0] = v.x;
-            d[4 * t + 1] = v.y;
-            d[4 * t + 2] = v.z;
-            d[4 * t + 3] = v.w;
-        }
-        d[16] = sh ? p[16] : 0u;
-    } else {
-#pragma unroll
-        for (int t = 0; t < 17; t++) d[t] = (4 * t < avail) ? p[t] : 0u;
+    for (int t = 0; t < 4; t++) {
+        const asj_u32x4 v = q[t];
+        d[4 * t + 0] = v.x;
+        d[4 * t + 1] = v.y;
+        d[4 * t + 2] = v.z;
+        d[4 * t + 3] = v.w;
     }
-    if (sh) {
+    d[16] = 0u;
+    if (sh) d[16] = p[16];
 #pragma unroll
-        for (int t = 0; t < 16; t++) kd[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], (uint32_t)sh);
-    } else {
+    for (int t = 0; t < 16; t++) kd[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], sh);
+}
+
+// Tail chunk: rem (1..63) key bytes at a; bytes at or past rem read as zero.
+__device__ __forceinline__ void asj_load_tail(const uint8_t *__restrict__ data, int64_t a, int rem, uint32_t kd[16])
+{
+    const uint32_t sh = (uint32_t)(a & 3);
+    const uint32_t *p = (const uint32_t *)(data + (a - sh));
+    const int avail = rem + (int)sh; // bytes from p through the key's end
+    uint32_t d[17];
 #pragma unroll
-        for (int t = 0; t < 16; t++) kd[t] = d[t];
+    for (int t = 0; t < 17; t++) d[t] = (4 * t < avail) ? p[t] : 0u;
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        const uint32_t w = __builtin_amdgcn_alignbyte(d[t + 1], d[t], sh);
+        const int nb = rem - 4 * t; // key bytes in this word
+        const uint32_t m = nb >= 4 ? 0xFFFFFFFFu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
+        kd[t] = w & m;
     }
-    const int64_t rem = len - k0;
-    if (rem < 64) {
+}
+
+// Largest i in [0, 64) with ex[i] <= x, for a non-decreasing ex[] in LDS
+// whose first entry is 0.
+__device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)
+{
+    int lo = 0, hi = ASJ_WAVE - 1;
 #pragma unroll
-        for (int t = 0; t < 16; t++) {
-            const int64_t nb = rem - 4 * t;
-            uint32_t m = nb >= 4 ? 0xFFFFFFFFu : (nb <= 0 ? 0u : ((1u << (8 * (int)nb)) - 1u));
-            kd[t] &= m;
-        }
+    for (int it = 0; it < 6; it++) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ex[mid] <= x) lo = mid;
+        else hi = mid - 1;
     }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------

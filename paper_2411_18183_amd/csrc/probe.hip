@@ -9,9 +9,10 @@
 // compared byte by byte unless verification is switched off).  The wave
 // advances all walks in rounds of at most one candidate per lane:
 //   1. candidates whose length differs from the probe key are rejected;
-//   2. the remaining pairs are cut into 64-byte key-relative chunks and laid
-//      out back to back; passes of 64 chunks compare one chunk per lane and
-//      flag mismatching pairs in LDS;
+//   2. the remaining pairs are cut into full 64-byte key-relative chunks,
+//      laid out back to back; passes of 64 chunks compare one chunk per lane
+//      and flag mismatching pairs in LDS; each lane then compares its own
+//      pair's partial last chunk;
 //   3. surviving pairs are appended to the output with one atomic add per
 //      wave and round (ballot + popcount prefix).
 // The baseline simple hash join walks the same way but treats every
@@ -28,8 +29,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a)
 {
     __shared__ int64_t crs[kWaves][ASJ_WAVE]; // candidate build key start
     __shared__ int64_t css[kWaves][ASJ_WAVE]; // probe key start
-    __shared__ int32_t clen[kWaves][ASJ_WAVE];
-    __shared__ int32_t cin[kWaves][ASJ_WAVE]; // inclusive prefix of chunk counts
+    __shared__ int32_t cex[kWaves][ASJ_WAVE]; // exclusive prefix of full-chunk counts
     __shared__ uint32_t cbad[kWaves][ASJ_WAVE];
 
     if (*a.table_status != 0) {
@@ -87,39 +87,44 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a)
                     lr = (int32_t)(a.roff[r + 1] - rs);
                 }
                 const bool eq = has && lr == ls;
-                const int nch = eq ? (ls + ASJ_CHUNK - 1) / ASJ_CHUNK : 0;
-                const int incl = asj_wave_incl_scan(nch);
+                // full 64-byte chunks of every pair, 64 per pass, one per lane
+                const int nfull = eq ? ls / ASJ_CHUNK : 0;
+                const int incl = asj_wave_incl_scan(nfull);
                 const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
                 crs[wave][lane] = rs;
                 css[wave][lane] = ss;
-                clen[wave][lane] = ls;
-                cin[wave][lane] = incl;
+                cex[wave][lane] = incl - nfull;
                 cbad[wave][lane] = 0;
                 asj_wave_sync();
                 for (int base = 0; base < total; base += ASJ_WAVE) {
                     const int x = base + lane;
                     if (x < total) {
-                        int lo = 0, hi = ASJ_WAVE - 1;
-#pragma unroll
-                        for (int it = 0; it < 6; it++) {
-                            const int mid = (lo + hi) >> 1;
-                            if (cin[wave][mid] > x) hi = mid;
-                            else lo = mid + 1;
-                        }
-                        const int i = lo;
-                        const int32_t L = clen[wave][i];
-                        const int c = x - (cin[wave][i] - (L + ASJ_CHUNK - 1) / ASJ_CHUNK);
+                        const int i = asj_find_owner(cex[wave], x);
+                        const int64_t k0 = (int64_t)(x - cex[wave][i]) * ASJ_CHUNK;
                         uint32_t kr[16], ks[16];
-                        asj_load_chunk(a.rdata, crs[wave][i], L, (int64_t)c * ASJ_CHUNK, kr);
-                        asj_load_chunk(a.sdata, css[wave][i], L, (int64_t)c * ASJ_CHUNK, ks);
+                        asj_load_full(a.rdata, crs[wave][i] + k0, kr);
+                        asj_load_full(a.sdata, css[wave][i] + k0, ks);
                         uint32_t diff = 0;
 #pragma unroll
                         for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
                         if (diff) cbad[wave][i] = 1u; // every writer stores the same value
                     }
                 }
+                // each lane compares its own pair's last, partial chunk
+                bool tail_ok = true;
+                const int rem = ls - nfull * ASJ_CHUNK;
+                if (eq && rem > 0) {
+                    const int64_t k0 = (int64_t)nfull * ASJ_CHUNK;
+                    uint32_t kr[16], ks[16];
+                    asj_load_tail(a.rdata, rs + k0, rem, kr);
+                    asj_load_tail(a.sdata, ss + k0, rem, ks);
+                    uint32_t diff = 0;
+#pragma unroll
+                    for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                    tail_ok = diff == 0;
+                }
                 asj_wave_sync();
-                ok = eq && cbad[wave][lane] == 0u;
+                ok = eq && tail_ok && cbad[wave][lane] == 0u;
                 asj_wave_sync();
             }
             const uint64_t om = __ballot(ok);

@@ -1,24 +1,26 @@
 // Signature of every key (Section 3.1), and the plain full-key hash of the
 // baseline simple hash join (Section 2), on gfx950.
 //
-// Work decomposition.  A key of len bytes is cut into ceil(len / 64)
-// key-relative chunks of 64 bytes.  A wave takes a window of 64 consecutive
-// keys, lays all their chunks out back to back and processes them in passes
-// of 64 chunks, one chunk per lane, so that short and long keys (16 B ..
-// 10 KB and beyond) keep every lane busy.  A lane reads its chunk with
-// 16-byte loads, realigns it to key-relative words, folds it into a partial
-// signature, scales the partial to the chunk's position in the key and
-// XORs it (GF addition) into the key's accumulator in LDS.
+// Work decomposition.  A key of len bytes is read as floor(len / 64) full
+// key-relative chunks of 64 bytes plus, when len % 64 != 0, one tail chunk.
+// A wave takes a window of 64 consecutive keys.  It lays the full chunks of
+// all 64 keys out back to back and processes them in passes of 64, one
+// chunk per lane, so short and long keys (16 B .. 10 KB and beyond) keep
+// every lane busy with identical, unpredicated code; a last pass gives lane
+// i the tail chunk of key i.  A lane reads its chunk with 16-byte loads,
+// realigns it to key-relative words, folds it into a partial signature,
+// scales the partial to the chunk's position in the key and XORs it (GF
+// addition) into the key's accumulator in LDS.
 //
 // Chunk arithmetic (GF(2^16), components j = 1, 2).  Component j of a chunk
 // is sum_u p_u alpha^(j u) over its 32 symbols.  Instead of one log/antilog
-// multiplication per symbol, the lane runs Horner's rule over groups of 8
+// multiplication per symbol, the lane runs Horner's rule over groups of
 // symbols with an unreduced accumulator: shifting by one bit is
-// multiplication by alpha = x, so a group costs shifts and XORs only, and
-// the bits that overflow 16 are folded back with one or two byte-indexed
-// table lookups (T[b] = b x^16).  Scaling a chunk to its position multiplies
-// by alpha^(32 j c) for chunk index c, done digit by digit with constant
-// tables (c = d0 + 8 d1 + 64 blk).
+// multiplication by alpha = x, so a group (16 symbols for j = 1, 8 for
+// j = 2) costs shifts and XORs only, and the 16 bits that overflow are
+// folded back with two byte-indexed table lookups (T[b] = b x^16).  Scaling
+// a chunk to its position multiplies by alpha^(32 j c) for chunk index c,
+// digit by digit with constant tables (c = d0 + 8 d1 + 64 blk).
 #include "asj_internal.h"
 
 namespace {
@@ -36,19 +38,30 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
 {
     const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
     uint32_t a1 = 0, a2 = 0;
+    // component 1: two groups of 16 symbols; p_v (v = 0..15 in the group)
+    // shifted by v stays below 2^31, plus the accumulator times x^16
 #pragma unroll
-    for (int q = 3; q >= 0; q--) {
-        const uint32_t w0 = kd[4 * q], w1 = kd[4 * q + 1], w2 = kd[4 * q + 2], w3 = kd[4 * q + 3];
-        // component 1: symbols p_v (v = 0..7 of the group) shifted by v
-        const uint32_t u1 = lo16(w0) ^ (hi16(w0) << 1) ^ (lo16(w1) << 2) ^ (hi16(w1) << 3) ^ (lo16(w2) << 4) ^
-                            (hi16(w2) << 5) ^ (lo16(w3) << 6) ^ (hi16(w3) << 7);
-        const uint32_t t1 = (a1 << 8) ^ u1; // < 2^24
-        a1 = (t1 & 0xFFFFu) ^ red[t1 >> 16];
-        if (NSYM == 2) {
-            // component 2: p_v shifted by 2v
-            const uint32_t u2 = lo16(w0) ^ (hi16(w0) << 2) ^ (lo16(w1) << 4) ^ (hi16(w1) << 6) ^ (lo16(w2) << 8) ^
-                                (hi16(w2) << 10) ^ (lo16(w3) << 12) ^ (hi16(w3) << 14);
-            const uint32_t t2 = (a2 << 16) ^ u2; // < 2^32
+    for (int g = 1; g >= 0; g--) {
+        uint32_t u = 0;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const uint32_t w = kd[8 * g + t];
+            u ^= (lo16(w) << (2 * t)) ^ (hi16(w) << (2 * t + 1));
+        }
+        const uint32_t t1 = (a1 << 16) ^ u;
+        a1 = (t1 & 0xFFFFu) ^ asj_cmul16(t1 >> 16, red);
+    }
+    if (NSYM == 2) {
+        // component 2: four groups of 8 symbols; p_v shifted by 2v stays below 2^30
+#pragma unroll
+        for (int q = 3; q >= 0; q--) {
+            uint32_t u = 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const uint32_t w = kd[4 * q + t];
+                u ^= (lo16(w) << (4 * t)) ^ (hi16(w) << (4 * t + 2));
+            }
+            const uint32_t t2 = (a2 << 16) ^ u;
             a2 = (t2 & 0xFFFFu) ^ asj_cmul16(t2 >> 16, red);
         }
     }
@@ -113,6 +126,14 @@ __device__ __forceinline__ uint32_t chunk_plain(const uint32_t kd[16], int c)
 }
 
 template <int MODE, int NSYM>
+__device__ __forceinline__ uint32_t chunk_value(const uint32_t kd[16], const uint16_t *tab, int c)
+{
+    if (MODE == ASJ_MODE_SIG16) return chunk_sig16<NSYM>(kd, tab, c);
+    if (MODE == ASJ_MODE_SIG8) return chunk_sig8<NSYM>(kd, tab, c);
+    return chunk_plain(kd, c);
+}
+
+template <int MODE, int NSYM>
 __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
                                                       const int64_t *__restrict__ off, int64_t n,
                                                       uint32_t *__restrict__ out, const uint16_t *__restrict__ gtab)
@@ -122,8 +143,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
                                                       : 2;
     __shared__ uint16_t tab[kTabWords];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
-    __shared__ int32_t klen[kWaves][ASJ_WAVE];
-    __shared__ int32_t kin[kWaves][ASJ_WAVE]; // inclusive prefix of chunk counts
+    __shared__ int32_t kex[kWaves][ASJ_WAVE]; // exclusive prefix of full-chunk counts
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE];
 
     if (MODE != ASJ_MODE_PLAIN) {
@@ -136,52 +156,47 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
     int64_t *wst = kst[wave];
-    int32_t *wlen = klen[wave];
-    int32_t *win_ = kin[wave];
+    int32_t *wex = kex[wave];
     uint32_t *wacc = kacc[wave];
 
     const int64_t nwin = (n + ASJ_WAVE - 1) / ASJ_WAVE;
     for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
         const int64_t k = w * ASJ_WAVE + lane;
         int64_t s = 0;
-        int32_t len = 0;
+        int len = 0;
         if (k < n) {
             s = off[k];
-            len = (int32_t)(off[k + 1] - s);
+            len = (int)(off[k + 1] - s);
         }
-        const int nch = (len + ASJ_CHUNK - 1) / ASJ_CHUNK;
-        const int incl = asj_wave_incl_scan(nch);
+        const int nfull = len / ASJ_CHUNK;
+        const int incl = asj_wave_incl_scan(nfull);
         const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
         wst[lane] = s;
-        wlen[lane] = len;
-        win_[lane] = incl;
+        wex[lane] = incl - nfull;
         wacc[lane] = 0;
         asj_wave_sync();
+        // full chunks of all 64 keys, 64 per pass, one per lane: uniform code
         for (int base = 0; base < total; base += ASJ_WAVE) {
             const int x = base + lane;
             if (x < total) {
-                int lo = 0, hi = ASJ_WAVE - 1; // smallest i with incl[i] > x
-#pragma unroll
-                for (int it = 0; it < 6; it++) {
-                    const int mid = (lo + hi) >> 1;
-                    if (win_[mid] > x) hi = mid;
-                    else lo = mid + 1;
-                }
-                const int i = lo;
-                const int32_t li = wlen[i];
-                const int c = x - (win_[i] - (li + ASJ_CHUNK - 1) / ASJ_CHUNK);
+                const int i = asj_find_owner(wex, x);
+                const int c = x - wex[i];
                 uint32_t kd[16];
-                asj_load_chunk(data, wst[i], li, (int64_t)c * ASJ_CHUNK, kd);
-                uint32_t v;
-                if (MODE == ASJ_MODE_SIG16) v = chunk_sig16<NSYM>(kd, tab, c);
-                else if (MODE == ASJ_MODE_SIG8) v = chunk_sig8<NSYM>(kd, tab, c);
-                else v = chunk_plain(kd, c);
-                atomicXor(&wacc[i], v);
+                asj_load_full(data, wst[i] + (int64_t)c * ASJ_CHUNK, kd);
+                atomicXor(&wacc[i], chunk_value<MODE, NSYM>(kd, tab, c));
             }
+        }
+        // tail pass: lane i takes key i's last, partial chunk
+        uint32_t v = 0;
+        const int rem = len - nfull * ASJ_CHUNK;
+        if (rem > 0) {
+            uint32_t kd[16];
+            asj_load_tail(data, s + (int64_t)nfull * ASJ_CHUNK, rem, kd);
+            v = chunk_value<MODE, NSYM>(kd, tab, nfull);
         }
         asj_wave_sync();
         if (k < n) {
-            uint32_t v = wacc[lane];
+            v ^= wacc[lane];
             if (MODE == ASJ_MODE_PLAIN) v = asj_mix32(v ^ ((uint32_t)len * 0xC2B2AE3Du));
             out[k] = v;
         }
