@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2411_18183_amd/csrc/sign.hip", "paper_2411_18183_amd/csrc/probe.hip",
+                  "paper_2411_18183_amd/csrc/sign_window.h",
                   "paper_2411_18183_amd/csrc/asj_internal.h"]
 
 WORKLOADS = {
@@ -61,21 +62,31 @@ def parse():
     ap.add_argument("--cpu-scale", type=float, default=0.25, help="size of the CPU oracle sample relative to the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain hash join comparison")
+    ap.add_argument("--batch-scale", type=float, default=0.25,
+                    help="size of the 256-join batch workload run beside the main line (0 = skip)")
+    ap.add_argument("--tiny-instances", type=int, default=128,
+                    help="independent tiny joins run as one batch beside the main line (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run the library's copy kernel over BYTES bytes (counter calibration)")
     return ap.parse_args()
 
 
 def algorithmic_bytes(name, n_keys, key_bytes, cap, n_pairs, verify_bytes):
-    """Bytes a phase must move once (see the design notes for the accounting)."""
+    """Bytes a phase must move once (see the design notes for the accounting).
+
+    verify_bytes is the sum of the build-key lengths over the result pairs:
+    the probe keys are read once for signing; their second read during
+    verification is served by the caches and is not compulsory."""
     if name.startswith("sign") or name.startswith("hash"):
         return key_bytes + 8 * (n_keys + 1) + 4 * n_keys
     if name == "table_init":
         return 8 * cap
     if name == "insert":
         return 4 * n_keys + 8 * n_keys
-    if name == "probe_verify":
-        return 8 * (n_keys + 1) + 4 * n_keys + 8 * n_keys + verify_bytes + 8 * n_pairs
+    if name in ("sign_probe_verify", "hash_probe_verify"):
+        # probe keys once + offsets + ids, >= one 32-byte slot group per key,
+        # build offsets and build key bytes of every pair, output pairs
+        return key_bytes + 8 * (n_keys + 1) + 4 * n_keys + 32 * n_keys + 16 * n_pairs + verify_bytes + 8 * n_pairs
     return 0
 
 
@@ -93,6 +104,110 @@ def run_steps(A, torch, Rk, Sk, out, counts, steps, flags=0):
     for name, ms in recs:
         per.setdefault(name, []).append(ms)
     return (t1 - t0) * 1e3 / steps, {k: sum(v) / len(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
+
+
+def tiny_instances(W, count: int, seed0: int = 1):
+    """count independent tiny joins (seeds seed0 ..) as one batch workload."""
+    import numpy as np
+    parts = [W.tiny(seed=seed0 + i) for i in range(count)]
+    def cat(rels):
+        lens = np.concatenate([r.lengths() for r in rels])
+        data = np.concatenate([r.data[:r.offsets[-1]] for r in rels] + [np.zeros(16, np.uint8)])
+        off = np.zeros(len(lens) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        ids = np.concatenate([r.ids for r in rels])
+        return W.Relation(data, off, ids)
+    R = cat([p.R for p in parts])
+    S = cat([p.S for p in parts])
+    r_seg = np.zeros(count + 1, dtype=np.int64)
+    s_seg = np.zeros(count + 1, dtype=np.int64)
+    r_seg[1:] = np.cumsum([p.R.n for p in parts])
+    s_seg[1:] = np.cumsum([p.S.n for p in parts])
+    return W.BatchWorkload(f"tiny x{count}", R, S, r_seg, s_seg, {"seed0": seed0})
+
+
+def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
+    """Batched launch sequence vs one asj_join per join, on the same inputs."""
+    import numpy as np
+    J = bw.njoins
+    R = A.DeviceKeys.from_host(bw.R)
+    S = A.DeviceKeys.from_host(bw.S)
+    out, oseg, counts, cands, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg)
+    dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
+    r_seg, s_seg, out_seg = dev(bw.r_seg), dev(bw.s_seg), dev(oseg)
+    cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
+    clock = torch.zeros(J + 1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n), dtype=torch.uint8, device="cuda")
+    run = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, clock, workspace=ws)
+    for _ in range(max(1, warmup)):
+        run()
+    torch.cuda.synchronize()
+    khz = A.clock_khz()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms_direct = (time.perf_counter() - t0) * 1e3 / steps
+    ck = clock.cpu().numpy()
+    lat = (ck[:-1] - ck[-1]) / khz  # ms after the batch started on the device
+    assert (cnt.cpu().numpy() == counts).all(), "batched counts changed between runs"
+    ms_graph = None
+    if graph:
+        st = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=st):
+            run()
+        for _ in range(max(1, warmup)):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+        assert (cnt.cpu().numpy() == counts).all(), "graph replay changed the counts"
+    # unbatched: the same joins one asj_join call at a time on one stream
+    rs_, ss_ = bw.r_seg, bw.s_seg
+    views = []
+    for j in range(J):
+        Rj = A.DeviceKeys(R.data, R.offsets[rs_[j]:rs_[j + 1] + 1], R.ids[rs_[j]:rs_[j + 1]] if R.ids is not None else None)
+        Sj = A.DeviceKeys(S.data, S.offsets[ss_[j]:ss_[j + 1] + 1], S.ids[ss_[j]:ss_[j + 1]] if S.ids is not None else None)
+        views.append((Rj, Sj, out[oseg[j]:oseg[j + 1]], torch.zeros(2, dtype=torch.int64, device="cuda")))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(J + 1)]
+    def unbatched(record=False):
+        if record:
+            ev[0].record()
+        for j, (Rj, Sj, oj, cj) in enumerate(views):
+            A.asj_join(Rj, Sj, oj, cj)
+            if record:
+                ev[j + 1].record()
+    unbatched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(max(1, steps // 4)):
+        unbatched(record=(i == 0))
+    torch.cuda.synchronize()
+    ms_unbatched = (time.perf_counter() - t0) * 1e3 / max(1, steps // 4)
+    lat_unb = np.array([ev[0].elapsed_time(ev[j + 1]) for j in range(J)])
+    ok = all(int(v[3][0]) == counts[j] for j, v in enumerate(views))
+    n_probe = int(bw.s_seg[-1])
+    key_bytes = bw.R.nbytes + bw.S.nbytes
+    best = min(ms_direct, ms_graph) if ms_graph else ms_direct
+    return {
+        "joins": J, "R": int(bw.r_seg[-1]), "S": n_probe, "key_bytes": int(key_bytes), "pairs": int(counts.sum()),
+        "ms_batched": round(ms_direct, 4), "ms_batched_graph": round(ms_graph, 4) if ms_graph else None,
+        "ms_unbatched": round(ms_unbatched, 4),
+        "value_batched": round(n_probe / (best * 1e-3), 1), "value_unbatched": round(n_probe / (ms_unbatched * 1e-3), 1),
+        "unit": "probe tuples/s", "key_gbps_batched": round(key_bytes / (best * 1e-3) / 1e9, 1),
+        "frac_peak_keys_batched": round(key_bytes / (best * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "join_latency_ms_batched": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                    "p99": round(float(np.percentile(lat, 99)), 4)},
+        "join_latency_ms_unbatched": {"p50": round(float(np.percentile(lat_unb, 50)), 4),
+                                      "p99": round(float(np.percentile(lat_unb, 99)), 4)},
+        "unbatched_counts_match": bool(ok),
+    }
 
 
 def main():
@@ -141,7 +256,7 @@ def main():
     pairs = out[:n_pairs].cpu().numpy()
     s_len = w.S.lengths()
     r_len = w.R.lengths()
-    verify_bytes = int(s_len[pairs[:, 1]].sum() + r_len[pairs[:, 0]].sum()) if n_pairs else 0
+    verify_bytes = int(r_len[pairs[:, 0]].sum()) if n_pairs else 0
     log(f"|T|={n_pairs} candidates={n_cand} (expected |T|={expected})")
 
     ms_step, phase_ms, phase_calls = run_steps(A, torch, Rk, Sk, out, counts, args.steps)
@@ -153,10 +268,10 @@ def main():
         tab_cap <<= 1
     nbytes = {
         "sign_build": algorithmic_bytes("sign_build", w.R.n, w.R.nbytes, tab_cap, n_pairs, verify_bytes),
-        "sign_probe_side": algorithmic_bytes("sign_probe_side", w.S.n, w.S.nbytes, tab_cap, n_pairs, verify_bytes),
+        "sign_probe_verify": algorithmic_bytes("sign_probe_verify", w.S.n, w.S.nbytes, tab_cap, n_pairs,
+                                               verify_bytes),
         "table_init": algorithmic_bytes("table_init", 0, 0, tab_cap, 0, 0),
         "insert": algorithmic_bytes("insert", w.R.n, 0, tab_cap, 0, 0),
-        "probe_verify": algorithmic_bytes("probe_verify", w.S.n, 0, tab_cap, n_pairs, verify_bytes),
     }
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_bytes = nbytes.get(dominant, 0)
@@ -201,6 +316,23 @@ def main():
         torch.cuda.synchronize()
         log(f"copy kernel over {nb} bytes done")
 
+    batched = None
+    if args.batch_scale > 0:
+        t = time.perf_counter()
+        bw = W.batch(scale=args.batch_scale)
+        log(f"generated batch J={bw.njoins} R={bw.R.n} S={bw.S.n} bytes={bw.R.nbytes + bw.S.nbytes} "
+            f"in {time.perf_counter() - t:.1f}s")
+        batched = bench_batch(A, torch, bw, max(3, args.steps // 2), args.warmup)
+        batched["workload"] = (f"batch of 256 joins at {args.batch_scale:g} scale: |R_j| log-uniform 100-200k, "
+                               f"|S_j| = U(1,8)|R_j|, XML-like keys log-uniform 16-2048 B, 25% copies")
+        log(f"batch: {batched}")
+    tiny_batch = None
+    if args.tiny_instances > 0:
+        tw = tiny_instances(W, args.tiny_instances)
+        tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup)
+        tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
+        log(f"tiny batch: {tiny_batch}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -239,6 +371,8 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "roofline": roofline,
         "plain_hash_join": plain,
+        "batched": batched,
+        "tiny_batched": tiny_batch,
         "cpu_baseline": cpu,
         "check": {"pairs_match_expected": n_pairs == expected and check == n_pairs},
     }

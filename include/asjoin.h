@@ -140,6 +140,59 @@ int asj_probe(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_
 int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
              int64_t *out_count, int64_t *cand_count, hipStream_t stream);
 
+/* ---- many independent joins in one launch sequence ---- */
+
+/* A batch of J independent equi-joins T_j = Join(R_j, S_j) (each one is the
+ * join of Section 2 / Figure 2 of Section 3.2).  All build rows of all joins
+ * share one key arena and all probe rows another; join j owns build rows
+ * r_seg[j] .. r_seg[j+1] of `r` and probe rows s_seg[j] .. s_seg[j+1] of
+ * `s`.  Tuple ids come from r.ids / s.ids (typically row-local ids) or are
+ * the global row indexes when those are NULL.
+ *   r, s        build and probe relations (device, see asj_keys)
+ *   r_seg       device int64[njoins + 1], non-decreasing, r_seg[0] = 0,
+ *               r_seg[njoins] = r.n
+ *   s_seg       device int64[njoins + 1], likewise over s
+ *   njoins      J >= 1
+ *   out         device asj_pair[]; join j writes out[out_seg[j] .. out_seg[j+1])
+ *   out_seg     device int64[njoins + 1], non-decreasing
+ *   out_count   device int64[njoins]: |T_j|, the full count even when it
+ *               exceeds join j's segment (pairs past it are not written)
+ *   cand_count  device int64[njoins] or NULL: signature-equal pairs per join
+ *   done_clock  device uint64[njoins + 1] or NULL: done_clock[j] = device
+ *               constant-clock time (asj_clock_khz) at which join j's last
+ *               probe row was finished, done_clock[njoins] = time at which the
+ *               batch started on the device
+ *   workspace   device memory of at least asj_batch_workspace_bytes(...)
+ *               bytes, or NULL to let the library allocate stream-ordered
+ *               (with a workspace the call allocates nothing, so it can be
+ *               captured into a HIP graph)
+ * Each join gets its own table segment (capacity = next power of two >=
+ * |R_j| / load_factor, at least 64).  Errors: ASJ_EINVAL, ASJ_ENOMEM,
+ * ASJ_EUNSUPPORTED, ASJ_EHIP. */
+typedef struct asj_batch {
+    asj_keys r;
+    asj_keys s;
+    const int64_t *r_seg;
+    const int64_t *s_seg;
+    int32_t njoins;
+    asj_pair *out;
+    const int64_t *out_seg;
+    int64_t *out_count;
+    int64_t *cand_count;
+    uint64_t *done_clock;
+    void *workspace;
+    int64_t workspace_bytes;
+} asj_batch;
+
+/* Device workspace needed by asj_join_batch for njoins joins over n_build
+ * build rows with these options (NULL = defaults); -1 on bad arguments. */
+int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, const asj_opts *opts);
+
+int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream);
+
+/* Frequency of the device constant clock used by done_clock, in kHz. */
+int64_t asj_clock_khz(void);
+
 /* Waits for the table's build work and returns ASJ_OK or ASJ_ETABLEFULL. */
 int asj_table_status(const asj_table *t);
 

@@ -48,6 +48,13 @@ class asj_opts(ctypes.Structure):
     _fields_ = [("sig", asj_sig_params), ("load_factor", ctypes.c_float), ("flags", ctypes.c_uint32)]
 
 
+class asj_batch(ctypes.Structure):
+    _fields_ = [("r", asj_keys), ("s", asj_keys), ("r_seg", ctypes.c_void_p), ("s_seg", ctypes.c_void_p),
+                ("njoins", ctypes.c_int32), ("out", ctypes.c_void_p), ("out_seg", ctypes.c_void_p),
+                ("out_count", ctypes.c_void_p), ("cand_count", ctypes.c_void_p), ("done_clock", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -72,8 +79,13 @@ def lib():
         L.asj_timing_enable.argtypes = [ctypes.c_int]
         L.asj_timing_read.argtypes = [P, P, ctypes.c_int]
         L.asj_util_copy.argtypes = [P, P, I64, P]
+        L.asj_batch_workspace_bytes.argtypes = [ctypes.c_int32, I64, ctypes.POINTER(asj_opts)]
+        L.asj_batch_workspace_bytes.restype = I64
+        L.asj_join_batch.argtypes = [ctypes.POINTER(asj_batch), ctypes.POINTER(asj_opts), P]
+        L.asj_clock_khz.argtypes = []
+        L.asj_clock_khz.restype = I64
         for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_table_status", "asj_table_free",
-                     "asj_timing_enable", "asj_timing_read", "asj_util_copy"):
+                     "asj_timing_enable", "asj_timing_read", "asj_util_copy", "asj_join_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -227,3 +239,72 @@ def timing_read(cap: int = 16):
 def asj_util_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
     _check(lib().asj_util_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes),
                                _stream(stream)), "asj_util_copy")
+
+
+# ---------------------------------------------------------------------------
+# batches of independent joins
+# ---------------------------------------------------------------------------
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def asj_batch_workspace_bytes(njoins: int, n_build: int, f: int = 16, nsym: int = 2, load_factor: float = 0.5,
+                              flags: int = 0) -> int:
+    o = _opts(f, nsym, load_factor, flags)
+    v = lib().asj_batch_workspace_bytes(int(njoins), int(n_build), ctypes.byref(o))
+    if v < 0:
+        raise AsjError(ASJ_EINVAL, "asj_batch_workspace_bytes")
+    return int(v)
+
+
+def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: torch.Tensor, out: torch.Tensor,
+                   out_seg: torch.Tensor, out_count: torch.Tensor, cand_count: Optional[torch.Tensor] = None,
+                   done_clock: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None, f: int = 16,
+                   nsym: int = 2, load_factor: float = 0.5, flags: int = 0, stream=None):
+    """Launch a batch of joins (see asj_batch in the header).  All tensors on the device:
+    r_seg/s_seg/out_seg int64 [J+1], out int32 [*, 2], out_count (and cand_count) int64 [J],
+    done_clock int64 [J+1] (device clock ticks), workspace uint8 (optional)."""
+    J = r_seg.numel() - 1
+    for t in (r_seg, s_seg, out_seg, out_count, cand_count, done_clock):
+        if t is not None and (not t.is_cuda or t.dtype != torch.int64 or not t.is_contiguous()):
+            raise ValueError("batch: segment, count and clock tensors must be contiguous cuda int64")
+    b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count),
+                  _ptr(cand_count), _ptr(done_clock), _ptr(workspace),
+                  int(workspace.numel()) if workspace is not None else 0)
+    o = _opts(f, nsym, load_factor, flags)
+    _check(lib().asj_join_batch(ctypes.byref(b), ctypes.byref(o), _stream(stream)), "asj_join_batch")
+
+
+def clock_khz() -> int:
+    return int(lib().asj_clock_khz())
+
+
+def join_batch(R: DeviceKeys, S: DeviceKeys, r_seg_host, s_seg_host, caps=None, **kw):
+    """Convenience batch join with the two-call pattern.
+
+    Returns (out int32 [*, 2] on the device, out_seg int64 numpy [J+1],
+    counts numpy [J], candidates numpy [J], done_clock numpy [J+1])."""
+    import numpy as np
+    dev = S.offsets.device
+    r_seg_host = np.asarray(r_seg_host, dtype=np.int64)
+    s_seg_host = np.asarray(s_seg_host, dtype=np.int64)
+    J = len(r_seg_host) - 1
+    if caps is None:
+        caps = np.diff(s_seg_host) + 16
+    r_seg = torch.from_numpy(r_seg_host).to(dev)
+    s_seg = torch.from_numpy(s_seg_host).to(dev)
+    for _ in range(2):
+        out_seg_host = np.zeros(J + 1, dtype=np.int64)
+        out_seg_host[1:] = np.cumsum(caps)
+        out_seg = torch.from_numpy(out_seg_host).to(dev)
+        out = torch.empty((max(int(out_seg_host[-1]), 1), 2), dtype=torch.int32, device=dev)
+        counts = torch.zeros(J, dtype=torch.int64, device=dev)
+        cands = torch.zeros(J, dtype=torch.int64, device=dev)
+        clock = torch.zeros(J + 1, dtype=torch.int64, device=dev)
+        asj_join_batch(R, S, r_seg, s_seg, out, out_seg, counts, cands, clock, **kw)
+        c = counts.cpu().numpy()
+        if (c <= caps).all():
+            break
+        caps = np.maximum(caps, c)
+    return out, out_seg_host, c, cands.cpu().numpy(), clock.cpu().numpy()

@@ -228,41 +228,28 @@ int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out
     hipError_t e = asj_launch_fill_i64(out_count, 1, 0, st);
     if (e == hipSuccess && cand_count) e = asj_launch_fill_i64(cand_count, 1, 0, st);
     if (e != hipSuccess) return hip_fail(e);
-    uint32_t *sig_s = nullptr;
-    e = alloc_async(&sig_s, (size_t)s->n, st);
-    if (e != hipSuccess) return hip_fail(e);
-    int out_rc = ASJ_OK;
-    do {
-        hipError_t le;
-        tim_begin(t->plain ? "hash_probe_side" : "sign_probe_side", st);
-        le = launch_sign_for(s, t->sig, t->plain, sig_s, g_dev[dev].tab, st);
-        tim_end(st);
-        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
-        asj_probe_args a = {};
-        a.rdata = t->r.data;
-        a.roff = t->r.offsets;
-        a.rids = t->r.ids;
-        a.sdata = s->data;
-        a.soff = s->offsets;
-        a.sids = s->ids;
-        a.n = s->n;
-        a.sig_s = sig_s;
-        a.slots = t->slots;
-        a.mask = (uint64_t)t->capacity - 1;
-        a.out = out;
-        a.cap = out_cap;
-        a.out_count = out_count;
-        a.cand_count = cand_count;
-        a.table_status = t->status;
-        a.plain = t->plain;
-        a.verify = t->verify;
-        tim_begin("probe_verify", st);
-        le = asj_launch_probe(&a, kProbeGridCap, st);
-        tim_end(st);
-        if (le != hipSuccess) { out_rc = hip_fail(le); break; }
-    } while (0);
-    (void)hipFreeAsync(sig_s, st);
-    return out_rc;
+    asj_probe_args a = {};
+    a.rdata = t->r.data;
+    a.roff = t->r.offsets;
+    a.rids = t->r.ids;
+    a.sdata = s->data;
+    a.soff = s->offsets;
+    a.sids = s->ids;
+    a.n = s->n;
+    a.slots = t->slots;
+    a.mask = (uint64_t)t->capacity - 1;
+    a.out = out;
+    a.cap = out_cap;
+    a.out_count = out_count;
+    a.cand_count = cand_count;
+    a.table_status = t->status;
+    a.plain = t->plain;
+    a.verify = t->verify;
+    const int mode = t->plain ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+    tim_begin(t->plain ? "hash_probe_verify" : "sign_probe_verify", st);
+    e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+    tim_end(st);
+    return e == hipSuccess ? ASJ_OK : hip_fail(e);
 }
 
 int table_free_impl(asj_table *t)
@@ -272,6 +259,53 @@ int table_free_impl(asj_table *t)
     hipError_t e2 = hipFreeAsync(t->status, t->stream);
     free(t);
     return (e1 == hipSuccess && e2 == hipSuccess) ? ASJ_OK : ASJ_EHIP;
+}
+
+// ---- batch workspace layout (each part 256-byte aligned) ----
+struct BatchLayout {
+    size_t desc, rows_done, total, status, sig, slots, bytes;
+    int64_t slot_bound;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool batch_layout(int32_t J, int64_t n_build, float lf, BatchLayout *L)
+{
+    if (J < 1 || n_build < 0 || !(lf > 0.0f && lf < 1.0f)) return false;
+    // every segment has capacity 64 or less than 2 |R_j| / lf
+    L->slot_bound = 64 * (int64_t)J + (int64_t)(2.0 * (double)n_build / lf) + 1;
+    size_t off = 0;
+    L->desc = off;
+    off = align256(off + sizeof(asj_join_desc) * (size_t)J);
+    L->rows_done = off;
+    off = align256(off + sizeof(int64_t) * (size_t)J);
+    L->total = off;
+    off = align256(off + sizeof(uint64_t));
+    L->status = off;
+    off = align256(off + sizeof(int32_t));
+    L->sig = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
+    L->slots = off;
+    off = align256(off + sizeof(uint64_t) * (size_t)L->slot_bound);
+    L->bytes = off;
+    return true;
+}
+
+int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf)
+{
+    asj_opts o = {};
+    if (opts) o = *opts;
+    *plain = (o.flags & ASJ_PLAIN) != 0;
+    *verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    if (*plain && !*verify) return ASJ_EINVAL;
+    *sig = asj_sig_params{16, 2};
+    if (!*plain) {
+        int rc = resolve_sig(o.sig, sig);
+        if (rc != ASJ_OK) return rc;
+    }
+    *lf = o.load_factor > 0.0f ? o.load_factor : 0.5f;
+    if (!(*lf > 0.0f && *lf < 1.0f)) return ASJ_EINVAL;
+    return ASJ_OK;
 }
 
 } // namespace
@@ -377,6 +411,106 @@ int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
     TimingScope ts;
     TIMED("copy", asj_launch_copy(dst, src, bytes, st));
     return ASJ_OK;
+}
+
+
+int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, const asj_opts *opts)
+{
+    int plain, verify;
+    asj_sig_params sig;
+    float lf;
+    if (batch_opts(opts, &plain, &verify, &sig, &lf) != ASJ_OK) return -1;
+    BatchLayout L;
+    if (!batch_layout(njoins, n_build, lf, &L)) return -1;
+    return (int64_t)L.bytes;
+}
+
+int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
+{
+    TimingScope ts;
+    if (!b || b->njoins < 1 || !keys_ok(&b->r) || !keys_ok(&b->s) || !b->r_seg || !b->s_seg || !b->out_seg ||
+        !b->out_count || !b->out)
+        return ASJ_EINVAL;
+    int plain, verify;
+    asj_sig_params sig;
+    float lf;
+    int rc = batch_opts(opts, &plain, &verify, &sig, &lf);
+    if (rc != ASJ_OK) return rc;
+    BatchLayout L;
+    if (!batch_layout(b->njoins, b->r.n, lf, &L)) return ASJ_EINVAL;
+    int dev = 0;
+    rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    uint8_t *ws = (uint8_t *)b->workspace;
+    bool owned = false;
+    if (ws) {
+        if (b->workspace_bytes < (int64_t)L.bytes || ((uintptr_t)ws & 255u)) return ASJ_EINVAL;
+    } else {
+        hipError_t e = hipMallocAsync((void **)&ws, L.bytes, st);
+        if (e != hipSuccess) return hip_fail(e);
+        owned = true;
+    }
+    asj_join_desc *desc = (asj_join_desc *)(ws + L.desc);
+    int64_t *rows_done = (int64_t *)(ws + L.rows_done);
+    uint64_t *total = (uint64_t *)(ws + L.total);
+    int32_t *status = (int32_t *)(ws + L.status);
+    uint32_t *sig_r = (uint32_t *)(ws + L.sig);
+    uint64_t *slots = (uint64_t *)(ws + L.slots);
+    int out_rc = ASJ_OK;
+    do {
+        hipError_t e;
+        tim_begin("batch_plan", st);
+        e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, lf, desc, rows_done, b->out_count, b->cand_count,
+                                  b->done_clock, total, st);
+        if (e == hipSuccess) e = asj_launch_fill_slots(slots, L.slot_bound, total, st);
+        if (e == hipSuccess) e = asj_launch_fill_i32(status, 1, 0, st);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        tim_begin(plain ? "hash_build" : "sign_build", st);
+        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        tim_begin("insert", st);
+        e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, b->njoins, desc, slots, status, st);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        asj_probe_args a = {};
+        a.rdata = b->r.data;
+        a.roff = b->r.offsets;
+        a.rids = b->r.ids;
+        a.sdata = b->s.data;
+        a.soff = b->s.offsets;
+        a.sids = b->s.ids;
+        a.n = b->s.n;
+        a.slots = slots;
+        a.out = b->out;
+        a.out_count = b->out_count;
+        a.cand_count = b->cand_count;
+        a.table_status = status;
+        a.plain = plain;
+        a.verify = verify;
+        a.njoins = b->njoins;
+        a.s_seg = b->s_seg;
+        a.desc = desc;
+        a.out_seg = b->out_seg;
+        a.rows_done = rows_done;
+        a.done_clock = b->done_clock;
+        const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+        tim_begin(plain ? "hash_probe_verify" : "sign_probe_verify", st);
+        e = asj_launch_probe(&a, mode, sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+    } while (0);
+    if (owned) (void)hipFreeAsync(ws, st);
+    return out_rc;
+}
+
+int64_t asj_clock_khz(void)
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return -1;
+    return (int64_t)v;
 }
 
 } // extern "C"

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/asjoin.h"
+#include "asjoin.h"
 
 #define ASJ_WAVE 64
 #define ASJ_CHUNK 64          // key bytes handled by one lane per pass
@@ -166,6 +166,25 @@ hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
 hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
                              int32_t *status, hipStream_t st);
 
+// Per-join table segment of a batch (written on the device by the plan kernel).
+struct asj_join_desc {
+    uint64_t tbase; // first slot of the join's segment
+    uint64_t mask;  // segment capacity - 1 (a power of two minus one)
+};
+
+// Largest j in [0, J) with seg[j] <= k, for a non-decreasing seg[] in device
+// memory (empty segments are skipped because a later equal entry wins).
+__device__ __forceinline__ int asj_find_seg(const int64_t *__restrict__ seg, int J, int64_t k)
+{
+    int lo = 0, hi = J - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 struct asj_probe_args {
     const uint8_t *rdata;
     const int64_t *roff;
@@ -174,7 +193,6 @@ struct asj_probe_args {
     const int64_t *soff;
     const int32_t *sids;
     int64_t n;
-    const uint32_t *sig_s;
     const uint64_t *slots;
     uint64_t mask;
     asj_pair *out;
@@ -184,6 +202,27 @@ struct asj_probe_args {
     const int32_t *table_status; // device; non-zero means the build failed
     int plain;
     int verify;
+    // batch of joins (njoins > 0): probe row k belongs to join j with
+    // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
+    // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its
+    // counters out_count[j], cand_count[j]
+    int32_t njoins;
+    const int64_t *s_seg;
+    const asj_join_desc *desc;
+    const int64_t *out_seg;
+    int64_t *rows_done;   // int64[njoins], zeroed: probe rows finished per join
+    uint64_t *done_clock; // uint64[njoins] or NULL
 };
-hipError_t asj_launch_probe(const asj_probe_args *a, int grid_cap, hipStream_t st);
+// Signs the probe keys and probes/verifies/compacts in one kernel.
+hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
+                            hipStream_t st);
 hipError_t asj_launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
+
+// Batch: per-join segment plan (capacities, prefix offsets, counters, start
+// clock), slot initialisation up to the planned total, batched inserts.
+hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, float load_factor,
+                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
+                                 uint64_t *done_clock, uint64_t *total_slots, hipStream_t st);
+hipError_t asj_launch_fill_slots(uint64_t *slots, int64_t bound, const uint64_t *total_slots, hipStream_t st);
+hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, int32_t njoins,
+                                   const asj_join_desc *desc, uint64_t *slots, int32_t *status, hipStream_t st);

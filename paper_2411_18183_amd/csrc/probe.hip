@@ -1,113 +1,195 @@
+// Probe side of the join in one kernel: Sign(s) for every probe tuple,
 // Probe(H_sign, s), candidate verification and output compaction
-// (Section 3.2, Figure 2: probe the table with every tuple of S and output
-// the matching tuples; Section 2: matching tuples are concatenated into T).
+// (Section 3.2, Figure 2: sign and probe every tuple of S and output the
+// matching tuples; Section 2: matching tuples are concatenated into T).
 //
-// One wave handles a window of 64 probe keys, one key per lane.  Each lane
-// walks its key's run of slots from the home slot mix32(signature) until the
-// first empty slot; every slot whose stored signature equals the key's is a
-// candidate (the paper outputs candidates directly; here each one is also
-// compared byte by byte unless verification is switched off).  The wave
-// advances all walks in rounds of at most one candidate per lane:
-//   1. candidates whose length differs from the probe key are rejected;
-//   2. the remaining pairs are cut into full 64-byte key-relative chunks,
-//      laid out back to back; passes of 64 chunks compare one chunk per lane
-//      and flag mismatching pairs in LDS; each lane then compares its own
-//      pair's partial last chunk;
-//   3. surviving pairs are appended to the output with one atomic add per
+// A wave takes a window of 64 probe keys, one key per lane.
+//   1. The window's keys are signed (sign_window.h), so the keys' bytes are
+//      still cache-resident when verification reads them again, and no
+//      signature array goes through memory.
+//   2. Each lane walks its key's run of slots from the home slot
+//      mix32(signature) to the first empty slot, reading the aligned group
+//      of four slots (32 bytes) that holds the current slot; every slot whose
+//      stored signature equals the key's is a candidate (the paper outputs
+//      candidates directly; here each one is compared byte by byte unless
+//      verification is switched off).  The wave advances all walks in rounds
+//      of at most one candidate per lane.
+//   3. A round rejects candidates whose length differs, cuts the remaining
+//      pairs into full 64-byte key-relative chunks laid out back to back
+//      (passes of 64 chunks, one per lane, mismatches flagged in LDS), and
+//      then lets every lane compare its own pair's partial last chunk.
+//   4. Surviving pairs are appended to the output with one atomic add per
 //      wave and round (ballot + popcount prefix).
-// The baseline simple hash join walks the same way but treats every
-// occupied slot as a candidate (no stored signature to filter with).
-#include "asj_internal.h"
+// The baseline simple hash join runs the same kernel with the plain key hash
+// and treats every occupied slot as a candidate (no signature stored).
+// In batch mode every lane finds its join (segment search over the probe
+// rows), probes that join's table segment and appends to that join's output
+// segment; emission then takes one atomic per wave, round and join, and the
+// wave that finishes a join's last probe row stamps its completion clock.
+#include "sign_window.h"
 
 namespace {
 
 constexpr int kBlock = 512;
 constexpr int kWaves = kBlock / ASJ_WAVE;
 
-template <int PLAIN, int VERIFY>
-__global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a)
-{
-    __shared__ int64_t crs[kWaves][ASJ_WAVE]; // candidate build key start
-    __shared__ int64_t css[kWaves][ASJ_WAVE]; // probe key start
-    __shared__ int32_t cex[kWaves][ASJ_WAVE]; // exclusive prefix of full-chunk counts
-    __shared__ uint32_t cbad[kWaves][ASJ_WAVE];
+typedef uint64_t asj_u64x2 __attribute__((ext_vector_type(2), aligned(16)));
+typedef uint64_t asj_u64x2a8 __attribute__((ext_vector_type(2), aligned(8)));
 
-    if (*a.table_status != 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.out_count = -1;
+struct Walk {
+    uint64_t h;     // next slot to examine
+    uint64_t qb;    // base slot of the cached group of four
+    uint64_t q[4];  // cached group
+    bool walking;   // the run has not ended yet
+};
+
+// Advance a lane's walk to its next candidate; true with *r = build row.
+template <int PLAIN>
+__device__ __forceinline__ bool next_candidate(const uint64_t *__restrict__ slots, uint64_t mask, uint32_t sg,
+                                               Walk &w, uint32_t &r)
+{
+    bool has = false;
+    while (w.walking) {
+        const uint64_t qb = w.h & ~3ull;
+        if (qb != w.qb) {
+            const asj_u64x2 *g = (const asj_u64x2 *)(slots + qb);
+            const asj_u64x2 lo = g[0], hi = g[1];
+            w.q[0] = lo.x;
+            w.q[1] = lo.y;
+            w.q[2] = hi.x;
+            w.q[3] = hi.y;
+            w.qb = qb;
+        }
+        const int p = (int)(w.h - qb);
+        bool stop = false;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (!stop && t >= p) {
+                const uint64_t sl = w.q[t];
+                if (sl == ASJ_EMPTY_SLOT) {
+                    w.walking = false;
+                    stop = true;
+                } else if (PLAIN || (uint32_t)(sl >> 32) == sg) {
+                    has = true;
+                    r = (uint32_t)sl;
+                    stop = true;
+                    w.h = (qb + t + 1) & mask;
+                    if (t < 3 && w.q[t + 1] == ASJ_EMPTY_SLOT) w.walking = false; // run ends here
+                }
+            }
+        }
+        if (stop) break;
+        w.h = (qb + 4) & mask;
+    }
+    return has;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, ASJ_WAVE);
+    return v;
+}
+
+template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH>
+__global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const uint16_t *__restrict__ gtab)
+{
+    __shared__ uint16_t tab[asj::TabWords<MODE>::value];
+    __shared__ int64_t kst[kWaves][ASJ_WAVE];  // probe key starts
+    __shared__ int64_t krs[kWaves][ASJ_WAVE];  // candidate build key starts
+    __shared__ int32_t kex[kWaves][ASJ_WAVE];  // exclusive prefix of full-chunk counts
+    __shared__ uint32_t kacc[kWaves][ASJ_WAVE]; // signature accumulators, then mismatch flags
+
+    if (*a.table_status != 0) { // same value for every thread: the whole grid leaves
+        if (!BATCH && blockIdx.x == 0 && threadIdx.x == 0) *a.out_count = -1;
         return;
     }
+    asj::load_tables<MODE, kBlock>(tab, gtab);
+
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+    int64_t *wst = kst[wave];
+    int64_t *wrs = krs[wave];
+    int32_t *wex = kex[wave];
+    uint32_t *wacc = kacc[wave];
     int64_t wave_cand = 0;
 
     const int64_t nwin = (a.n + ASJ_WAVE - 1) / ASJ_WAVE;
-    for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
-        const int64_t k = w * ASJ_WAVE + lane;
+    for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += (int64_t)gridDim.x * kWaves) {
+        const int64_t k = win * ASJ_WAVE + lane;
         const bool valid = k < a.n;
         int64_t ss = 0;
-        int32_t ls = 0;
-        uint32_t sg = 0;
-        uint64_t h = 0;
+        int ls = 0;
         int32_t sid = 0;
+        // the lane's join: its table segment and its output segment
+        int j = 0;
+        const uint64_t *slots = a.slots;
+        uint64_t mask = a.mask;
+        asj_pair *out = a.out;
+        int64_t cap = a.cap;
+        int64_t *count = a.out_count;
         if (valid) {
             ss = a.soff[k];
-            ls = (int32_t)(a.soff[k + 1] - ss);
-            sg = a.sig_s[k];
-            h = asj_mix32(sg) & a.mask;
+            ls = (int)(a.soff[k + 1] - ss);
             sid = a.sids ? a.sids[k] : (int32_t)k;
-        }
-        bool walking = valid;
-        for (;;) {
-            bool has = false;
-            uint32_t r = 0;
-            while (walking) {
-                const uint64_t slot = a.slots[h];
-                if (slot == ASJ_EMPTY_SLOT) {
-                    walking = false;
-                    break;
-                }
-                h = (h + 1) & a.mask;
-                if (PLAIN || (uint32_t)(slot >> 32) == sg) {
-                    has = true;
-                    r = (uint32_t)slot;
-                    break;
-                }
+            if (BATCH) {
+                j = asj_find_seg(a.s_seg, a.njoins, k);
+                const asj_join_desc d = a.desc[j];
+                slots = a.slots + d.tbase;
+                mask = d.mask;
+                const int64_t o0 = a.out_seg[j];
+                out = a.out + o0;
+                cap = a.out_seg[j + 1] - o0;
+                count = a.out_count + j;
             }
+        }
+        const uint32_t sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab);
+
+        Walk wk;
+        wk.h = asj_mix32(sg) & mask;
+        wk.qb = ~0ull;
+        wk.walking = valid;
+        int lane_cand = 0;
+        for (;;) {
+            uint32_t r = 0;
+            const bool has = next_candidate<PLAIN>(slots, mask, sg, wk, r);
             const uint64_t hm = __ballot(has);
             if (hm == 0) break;
             wave_cand += __popcll(hm);
+            lane_cand += has ? 1 : 0;
 
             bool ok = has;
             if (VERIFY) {
                 int64_t rs = 0;
-                int32_t lr = -1;
+                int lr = -1;
                 if (has) {
-                    rs = a.roff[r];
-                    lr = (int32_t)(a.roff[r + 1] - rs);
+                    const asj_u64x2a8 o = *(const asj_u64x2a8 *)(a.roff + r); // offsets r, r + 1
+                    rs = (int64_t)o.x;
+                    lr = (int)((int64_t)o.y - rs);
                 }
                 const bool eq = has && lr == ls;
-                // full 64-byte chunks of every pair, 64 per pass, one per lane
+                // full 64-byte chunks of every equal-length pair, one per lane
                 const int nfull = eq ? ls / ASJ_CHUNK : 0;
                 const int incl = asj_wave_incl_scan(nfull);
                 const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
-                crs[wave][lane] = rs;
-                css[wave][lane] = ss;
-                cex[wave][lane] = incl - nfull;
-                cbad[wave][lane] = 0;
+                wst[lane] = ss;
+                wrs[lane] = rs;
+                wex[lane] = incl - nfull;
+                wacc[lane] = 0;
                 asj_wave_sync();
                 for (int base = 0; base < total; base += ASJ_WAVE) {
                     const int x = base + lane;
                     if (x < total) {
-                        const int i = asj_find_owner(cex[wave], x);
-                        const int64_t k0 = (int64_t)(x - cex[wave][i]) * ASJ_CHUNK;
+                        const int i = asj_find_owner(wex, x);
+                        const int64_t k0 = (int64_t)(x - wex[i]) * ASJ_CHUNK;
                         uint32_t kr[16], ks[16];
-                        asj_load_full(a.rdata, crs[wave][i] + k0, kr);
-                        asj_load_full(a.sdata, css[wave][i] + k0, ks);
+                        asj_load_full(a.rdata, wrs[i] + k0, kr);
+                        asj_load_full(a.sdata, wst[i] + k0, ks);
                         uint32_t diff = 0;
 #pragma unroll
                         for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
-                        if (diff) cbad[wave][i] = 1u; // every writer stores the same value
+                        if (diff) wacc[i] = 1u; // every writer stores the same value
                     }
                 }
                 // each lane compares its own pair's last, partial chunk
@@ -124,46 +206,86 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a)
                     tail_ok = diff == 0;
                 }
                 asj_wave_sync();
-                ok = eq && tail_ok && cbad[wave][lane] == 0u;
+                ok = eq && tail_ok && wacc[lane] == 0u;
                 asj_wave_sync();
             }
-            const uint64_t om = __ballot(ok);
-            if (om) {
+            // append the survivors: one atomic per wave, round and join
+            uint64_t pend = __ballot(ok);
+            while (pend) {
+                const int leader = __ffsll((unsigned long long)pend) - 1;
+                const int lj = __shfl(j, leader, ASJ_WAVE);
+                const bool mine = ok && (!BATCH || j == lj);
+                const uint64_t m = __ballot(mine);
                 unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd((unsigned long long *)a.out_count, (unsigned long long)__popcll(om));
-                base = __shfl(base, 0, ASJ_WAVE);
-                if (ok) {
-                    const int64_t idx = (int64_t)base + __popcll(om & lanemask_lt);
-                    if (idx < a.cap) {
+                if (lane == leader) base = atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(m));
+                base = __shfl(base, leader, ASJ_WAVE);
+                if (mine) {
+                    const int64_t idx = (int64_t)base + __popcll(m & lanemask_lt);
+                    if (idx < cap) {
                         asj_pair p;
                         p.r_id = a.rids ? a.rids[r] : (int32_t)r;
                         p.s_id = sid;
-                        a.out[idx] = p;
+                        out[idx] = p;
                     }
                 }
+                pend &= ~m;
+            }
+        }
+        if (BATCH) {
+            // per-join candidate counts and completion clocks
+            uint64_t pend = __ballot(valid);
+            while (pend) {
+                const int leader = __ffsll((unsigned long long)pend) - 1;
+                const int lj = __shfl(j, leader, ASJ_WAVE);
+                const bool mine = valid && j == lj;
+                const uint64_t m = __ballot(mine);
+                const int cands = wave_sum(mine ? lane_cand : 0);
+                if (lane == leader) {
+                    if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + lj), (unsigned long long)cands);
+                    const unsigned long long rows = __popcll(m);
+                    const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + lj), rows);
+                    if (a.done_clock && (int64_t)(before + rows) == a.s_seg[lj + 1] - a.s_seg[lj])
+                        a.done_clock[lj] = wall_clock64();
+                }
+                pend &= ~m;
             }
         }
     }
-    if (a.cand_count && lane == 0 && wave_cand)
+    if (!BATCH && a.cand_count && lane == 0 && wave_cand)
         atomicAdd((unsigned long long *)a.cand_count, (unsigned long long)wave_cand);
 }
 
-template <int PLAIN, int VERIFY>
-hipError_t launch(const asj_probe_args *a, int grid_cap, hipStream_t st)
+template <int MODE, int NSYM, int PLAIN, int VERIFY>
+hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
     const int64_t nwin = (a->n + ASJ_WAVE - 1) / ASJ_WAVE;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((probe_kernel<PLAIN, VERIFY>), dim3((unsigned)blocks), dim3(kBlock), 0, st, *a);
+    if (a->njoins > 0)
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           *a, tab);
+    else
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           *a, tab);
     return hipGetLastError();
+}
+
+template <int MODE, int NSYM>
+hipError_t launch_sig(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
+{
+    return a->verify ? launch<MODE, NSYM, 0, 1>(a, tab, grid_cap, st) : launch<MODE, NSYM, 0, 0>(a, tab, grid_cap, st);
 }
 
 } // namespace
 
-hipError_t asj_launch_probe(const asj_probe_args *a, int grid_cap, hipStream_t st)
+hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
+                            hipStream_t st)
 {
-    if (a->plain) return launch<1, 1>(a, grid_cap, st);
-    if (a->verify) return launch<0, 1>(a, grid_cap, st);
-    return launch<0, 0>(a, grid_cap, st);
+    if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1>(a, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch_sig<ASJ_MODE_SIG16, 2>(a, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch_sig<ASJ_MODE_SIG16, 1>(a, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch_sig<ASJ_MODE_SIG8, 4>(a, tab, grid_cap, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 2) return launch_sig<ASJ_MODE_SIG8, 2>(a, tab, grid_cap, st);
+    return hipErrorInvalidValue;
 }

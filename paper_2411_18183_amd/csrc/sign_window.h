@@ -1,0 +1,197 @@
+// Per-window signing shared by the signature kernel and the fused probe
+// kernel (included by sign.hip and probe.hip).
+//
+// Work decomposition.  A key of len bytes is read as floor(len / 64) full
+// key-relative chunks of 64 bytes plus, when len % 64 != 0, one tail chunk.
+// A wave takes a window of 64 consecutive keys.  It lays the full chunks of
+// all 64 keys out back to back and processes them in passes of 64, one
+// chunk per lane, so short and long keys (16 B .. 10 KB and beyond) keep
+// every lane busy with identical, unpredicated code; a last pass gives lane
+// i the tail chunk of key i.  A lane reads its chunk with 16-byte loads,
+// realigns it to key-relative words, folds it into a partial signature,
+// scales the partial to the chunk's position in the key and XORs it (GF
+// addition) into the key's accumulator in LDS.
+//
+// Chunk arithmetic (GF(2^16), components j = 1, 2).  Component j of a chunk
+// is sum_u p_u alpha^(j u) over its 32 symbols.  Instead of one log/antilog
+// multiplication per symbol, the lane runs Horner's rule over groups of
+// symbols with an unreduced accumulator: shifting by one bit is
+// multiplication by alpha = x, so a group (16 symbols for j = 1, 8 for
+// j = 2) costs shifts and XORs only, and the 16 bits that overflow are
+// folded back with two byte-indexed table lookups (T[b] = b x^16).  Scaling
+// a chunk to its position multiplies by alpha^(32 j c) for chunk index c,
+// digit by digit with constant tables (c = d0 + 8 d1 + 64 blk).
+#pragma once
+
+#include "asj_internal.h"
+
+namespace asj {
+
+__device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
+
+// GF(2^16): both components of one 64-byte chunk, positions relative to the
+// chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
+template <int NSYM>
+__device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
+{
+    const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
+    uint32_t a1 = 0, a2 = 0;
+    // component 1: two groups of 16 symbols; p_v (v = 0..15 in the group)
+    // shifted by v stays below 2^31, plus the accumulator times x^16
+#pragma unroll
+    for (int g = 1; g >= 0; g--) {
+        uint32_t u = 0;
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const uint32_t w = kd[8 * g + t];
+            u ^= (lo16(w) << (2 * t)) ^ (hi16(w) << (2 * t + 1));
+        }
+        const uint32_t t1 = (a1 << 16) ^ u;
+        a1 = (t1 & 0xFFFFu) ^ asj_cmul16(t1 >> 16, red);
+    }
+    if (NSYM == 2) {
+        // component 2: four groups of 8 symbols; p_v shifted by 2v stays below 2^30
+#pragma unroll
+        for (int q = 3; q >= 0; q--) {
+            uint32_t u = 0;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const uint32_t w = kd[4 * q + t];
+                u ^= (lo16(w) << (4 * t)) ^ (hi16(w) << (4 * t + 2));
+            }
+            const uint32_t t2 = (a2 << 16) ^ u;
+            a2 = (t2 & 0xFFFFu) ^ asj_cmul16(t2 >> 16, red);
+        }
+    }
+    // position of the chunk in the key: multiply by alpha^(32 j c)
+    const int d0 = c & 7, d1 = (c >> 3) & 7;
+    a1 = asj_cmul16(a1, tab + asj_tab_d0(1, d0) * ASJ_TAB_WORDS);
+    a1 = asj_cmul16(a1, tab + asj_tab_d1(1, d1) * ASJ_TAB_WORDS);
+    if (NSYM == 2) {
+        a2 = asj_cmul16(a2, tab + asj_tab_d0(2, d0) * ASJ_TAB_WORDS);
+        a2 = asj_cmul16(a2, tab + asj_tab_d1(2, d1) * ASJ_TAB_WORDS);
+    }
+    for (int blk = c >> 6; blk > 0; blk--) {
+        a1 = asj_cmul16(a1, tab + asj_tab_blk(1) * ASJ_TAB_WORDS);
+        if (NSYM == 2) a2 = asj_cmul16(a2, tab + asj_tab_blk(2) * ASJ_TAB_WORDS);
+    }
+    return a1 | (a2 << 16);
+}
+
+// GF(2^8): byte symbols, NSYM components of 8 bits; component j of the chunk
+// is sum_u b_u alpha^(j u), u = 0..63, then scaled by alpha^(64 j c).
+template <int NSYM>
+__device__ __forceinline__ uint32_t chunk_sig8(const uint32_t kd[16], const uint16_t *__restrict__ t8, int c)
+{
+    const uint16_t *ex = t8 + ASJ_TAB8_EXP, *lg = t8 + ASJ_TAB8_LOG, *red = t8 + ASJ_TAB8_RED;
+    uint32_t acc[NSYM];
+#pragma unroll
+    for (int j = 0; j < NSYM; j++) acc[j] = 0;
+#pragma unroll
+    for (int t = 15; t >= 0; t--) {
+        const uint32_t w = kd[t];
+        const uint32_t b0 = w & 255u, b1 = (w >> 8) & 255u, b2 = (w >> 16) & 255u, b3 = w >> 24;
+#pragma unroll
+        for (int j = 1; j <= NSYM; j++) {
+            // four symbols per word: Horner step by alpha^(4j), unreduced
+            const uint32_t u = b0 ^ (b1 << j) ^ (b2 << (2 * j)) ^ (b3 << (3 * j));
+            const uint32_t T = (acc[j - 1] << (4 * j)) ^ u; // < 2^(8 + 4j) <= 2^24
+            uint32_t v = (T & 255u) ^ red[(T >> 8) & 255u];
+            if (j > 2) v ^= red[256 + ((T >> 16) & 255u)];
+            acc[j - 1] = v;
+        }
+    }
+    uint32_t out = 0;
+#pragma unroll
+    for (int j = 1; j <= NSYM; j++) {
+        uint32_t v = acc[j - 1];
+        if (v) v = ex[(lg[v] + (uint32_t)((64ull * j * (uint64_t)c) % 255u)) % 255u];
+        out |= v << (8 * (j - 1));
+    }
+    return out;
+}
+
+// Plain multiplicative hash of one chunk, seeded by its index (baseline).
+__device__ __forceinline__ uint32_t chunk_plain(const uint32_t kd[16], int c)
+{
+    uint32_t h = 0x9E3779B9u * (uint32_t)(c + 1);
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        h = (h ^ kd[t]) * 0x85EBCA77u;
+        h ^= h >> 15;
+    }
+    return h;
+}
+
+template <int MODE, int NSYM>
+__device__ __forceinline__ uint32_t chunk_value(const uint32_t kd[16], const uint16_t *tab, int c)
+{
+    if (MODE == ASJ_MODE_SIG16) return chunk_sig16<NSYM>(kd, tab, c);
+    if (MODE == ASJ_MODE_SIG8) return chunk_sig8<NSYM>(kd, tab, c);
+    return chunk_plain(kd, c);
+}
+
+// Words of the constant tables a block keeps in LDS for each mode.
+template <int MODE>
+struct TabWords {
+    static constexpr int value = MODE == ASJ_MODE_SIG16 ? ASJ_NTAB16 * ASJ_TAB_WORDS
+                                 : MODE == ASJ_MODE_SIG8 ? ASJ_NTAB8 * ASJ_TAB_WORDS
+                                                         : 2;
+};
+
+// Copy the mode's constant tables from device memory into LDS (whole block).
+template <int MODE, int BLOCK>
+__device__ __forceinline__ void load_tables(uint16_t *tab, const uint16_t *__restrict__ gtab)
+{
+    if (MODE == ASJ_MODE_PLAIN) return;
+    constexpr int words = TabWords<MODE>::value;
+    const uint16_t *src = gtab + (MODE == ASJ_MODE_SIG8 ? ASJ_TAB8_BASE : 0);
+    for (int i = threadIdx.x; i < words / 2; i += BLOCK)
+        reinterpret_cast<uint32_t *>(tab)[i] = reinterpret_cast<const uint32_t *>(src)[i];
+    __syncthreads();
+}
+
+// Signature (or finalized plain hash) of each lane's key for a window of 64
+// keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes without
+// a key).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays.
+template <int MODE, int NSYM>
+__device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len,
+                                                int64_t *wst, int32_t *wex, uint32_t *wacc,
+                                                const uint16_t *tab)
+{
+    const int lane = threadIdx.x % ASJ_WAVE;
+    const int nfull = len / ASJ_CHUNK;
+    const int incl = asj_wave_incl_scan(nfull);
+    const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
+    wst[lane] = s;
+    wex[lane] = incl - nfull;
+    wacc[lane] = 0;
+    asj_wave_sync();
+    // full chunks of all 64 keys, 64 per pass, one per lane: uniform code
+    for (int base = 0; base < total; base += ASJ_WAVE) {
+        const int x = base + lane;
+        if (x < total) {
+            const int i = asj_find_owner(wex, x);
+            const int c = x - wex[i];
+            uint32_t kd[16];
+            asj_load_full(data, wst[i] + (int64_t)c * ASJ_CHUNK, kd);
+            atomicXor(&wacc[i], chunk_value<MODE, NSYM>(kd, tab, c));
+        }
+    }
+    // tail pass: lane i takes key i's last, partial chunk
+    uint32_t v = 0;
+    const int rem = len - nfull * ASJ_CHUNK;
+    if (rem > 0) {
+        uint32_t kd[16];
+        asj_load_tail(data, s + (int64_t)nfull * ASJ_CHUNK, rem, kd);
+        v = chunk_value<MODE, NSYM>(kd, tab, nfull);
+    }
+    asj_wave_sync();
+    v ^= wacc[lane];
+    asj_wave_sync();
+    if (MODE == ASJ_MODE_PLAIN) v = asj_mix32(v ^ ((uint32_t)len * 0xC2B2AE3Du));
+    return v;
+}
+
+} // namespace asj
