@@ -66,6 +66,9 @@ def parse():
                     help="size of the 256-join batch workload run beside the main line (0 = skip)")
     ap.add_argument("--tiny-instances", type=int, default=128,
                     help="independent tiny joins run as one batch beside the main line (0 = skip)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="size of the resident build side of the serving run (1.0 = 10M keys; 0 = skip)")
+    ap.add_argument("--serve-arrivals", type=int, default=48)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run the library's copy kernel over BYTES bytes (counter calibration)")
     return ap.parse_args()
@@ -210,6 +213,83 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
     }
 
 
+def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, seed: int = 5):
+    """Continuous-batching server over a resident build table, Poisson arrivals."""
+    import numpy as np
+    t = time.perf_counter()
+    R = W.served_build_side(seed=seed, scale=scale)
+    Rk = A.DeviceKeys.from_host(R)
+    table = A.asj_build(Rk)
+    payloads = [W.served_request(R, seed=seed, request=i) for i in range(n_payloads)]
+    pins = [(torch.from_numpy(q.data).pin_memory(), torch.from_numpy(q.offsets).pin_memory()) for q in payloads]
+    nmax = max(q.n for q in payloads)
+    outs = [torch.empty((nmax, 2), dtype=torch.int32).pin_memory() for _ in range(arrivals)]
+    torch.cuda.synchronize()
+    log(f"serving: R={R.n} payloads={n_payloads} keys={sum(q.n for q in payloads)} "
+        f"bytes={sum(q.nbytes for q in payloads)} prepared in {time.perf_counter() - t:.1f}s")
+    expect = None
+
+    def run(srv, rate_per_s=None, count=arrivals):
+        order = [i % n_payloads for i in range(count)]
+        times = W.poisson_arrivals(seed + 100, rate_per_s, count) if rate_per_s else np.zeros(count)
+        tickets = []
+        t0 = time.perf_counter()
+        for i, p in enumerate(order):
+            while time.perf_counter() - t0 < times[i]:
+                pass
+            d, o = pins[p]
+            tickets.append(srv.submit(d, o, outs[i][:payloads[p].n]))
+        infos = [srv.wait(x) for x in tickets]
+        lat = np.array([x["t_done_ms"] - x["t_arrive_ms"] for x in infos])
+        span = max(x["t_done_ms"] for x in infos) - min(x["t_arrive_ms"] for x in infos)
+        counts = [x["count"] for x in infos]
+        assert all(x["status"] == 0 for x in infos)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "throughput_req_s": round(count / (span * 1e-3), 1),
+                "probe_tuples_s": round(sum(payloads[p].n for p in order) / (span * 1e-3), 1),
+                "mean_batch": round(float(np.mean([x["batch_requests"] for x in infos])), 2)}, order, counts
+
+    serial = A.Server(table, slots=1, max_batch_requests=1)
+    run(serial, count=min(8, arrivals))
+    sat_serial, order, counts = run(serial)
+    serial.close()
+    expect = {p: c for p, c in zip(order, counts)}
+    cb = A.Server(table, slots=4)
+    run(cb, count=min(8, arrivals))
+    sat_cb, order, counts = run(cb)
+    assert all(expect[p] == c for p, c in zip(order, counts)), "results differ between servers"
+    mu = sat_cb["throughput_req_s"]
+    sweep = []
+    for f in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1):
+        res, order, counts = run(cb, rate_per_s=f * mu)
+        assert all(expect[p] == c for p, c in zip(order, counts))
+        res["load"] = f
+        res["rate_req_s"] = round(f * mu, 1)
+        sweep.append(res)
+    cb.close()
+    serial = A.Server(table, slots=1, max_batch_requests=1)
+    serial_sweep = []
+    for f in (0.5, 0.9):
+        res, order, counts = run(serial, rate_per_s=f * mu)
+        res["load"] = f
+        serial_sweep.append(res)
+    serial.close()
+    need = [q.nbytes + 20 * q.n + (1 << 12) for q in payloads]  # a request's device footprint, rounded up
+    small_budget = int(max(2.0 * float(np.mean(need)), 1.1 * max(need)))
+    sb = A.Server(table, slots=4, hbm_budget=small_budget)
+    small, order, counts = run(sb, rate_per_s=0.7 * mu)
+    small["budget_bytes"] = small_budget
+    small["peak_budget_used"] = sb.stats()["peak_budget_used"]
+    assert small["peak_budget_used"] <= small_budget
+    sb.close()
+    table.free()
+    return {"workload": f"resident R={R.n} x 256 B printable; {n_payloads} request payloads of log-uniform "
+                        f"10k-1M keys (30% copies of R rows, 70% fresh 64-1024 B); {arrivals} arrivals per point",
+            "saturation_serial": sat_serial, "saturation_continuous": sat_cb, "sweep_continuous": sweep,
+            "sweep_serial": serial_sweep, "small_budget": small,
+            "note": "latency = completion (results in pinned host memory) - submission, host-to-device copies included"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -333,6 +413,11 @@ def main():
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
         log(f"tiny batch: {tiny_batch}")
 
+    served = None
+    if args.serve_scale > 0:
+        served = bench_serving(A, torch, W, args.serve_scale, 16, args.serve_arrivals)
+        log(f"serving: {served}")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -373,6 +458,7 @@ def main():
         "plain_hash_join": plain,
         "batched": batched,
         "tiny_batched": tiny_batch,
+        "served": served,
         "cpu_baseline": cpu,
         "check": {"pairs_match_expected": n_pairs == expected and check == n_pairs},
     }

@@ -193,6 +193,68 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream)
 /* Frequency of the device constant clock used by done_clock, in kHz. */
 int64_t asj_clock_khz(void);
 
+/* ---- serving: probe requests against a resident build table ---- */
+
+/* A request server over one built table (the probe phase of Section 3.2,
+ * Figure 2, applied to a stream of probe relations).  Requests are admitted
+ * first-in first-out when the device bytes they need fit in hbm_budget;
+ * everything admitted while a stream slot is free is packed into one
+ * batched probe launch (continuous batching: requests that arrive while
+ * others are on the device join the next launch on the next free slot and
+ * overlap with the running ones).  Results are identical to asj_probe on the
+ * request alone. */
+typedef struct asj_server asj_server;
+
+typedef struct asj_server_opts {
+    int32_t slots;              /* concurrent launches (HIP streams); <= 0 means 4 */
+    int64_t hbm_budget;         /* device bytes admitted requests may hold; <= 0 means 200 GiB */
+    int64_t max_batch_keys;     /* probe keys packed into one launch; <= 0 means 4Mi */
+    int32_t max_batch_requests; /* requests packed into one launch; <= 0 means 256 (1 = no packing) */
+    int32_t dry_run;            /* nonzero: no device work; a launch completes after dry_ns_per_key
+                                   nanoseconds per probe key (exercises the scheduler without a GPU;
+                                   results are then empty) */
+    double dry_ns_per_key;
+} asj_server_opts;
+
+/* Outcome of one request; times are milliseconds on the server's steady clock. */
+typedef struct asj_request_info {
+    int32_t status;         /* ASJ_OK or the error that ended the request */
+    int64_t count;          /* |T| of the request, even when larger than its out_cap */
+    double t_arrive_ms;     /* submission */
+    double t_launch_ms;     /* admission into a launch */
+    double t_done_ms;       /* results in the caller's buffer */
+    int32_t batch_id;       /* launch sequence number */
+    int32_t batch_requests; /* requests packed into that launch */
+} asj_request_info;
+
+typedef struct asj_server_stats_t {
+    int64_t queued, busy_slots, budget_used, peak_budget_used, launches;
+    double now_ms;
+} asj_server_stats_t;
+
+/* t: a built table (its build stream is synchronized here); the server
+ * borrows it until asj_server_destroy.  t may be NULL with dry_run. */
+int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_server **out);
+
+/* Queue one request.  HOST pointers: probe key k is data[offsets[k] ..
+ * offsets[k+1]) (offsets[0] may be non-zero), results go to out[0 ..
+ * out_cap) as (r_id, s_id) with s_id the row index inside the request.
+ * The caller keeps data, offsets and out alive and unchanged until
+ * asj_server_wait returns for the ticket; pinned memory (hipHostMalloc)
+ * lets the copies overlap.  Returns ASJ_ENOMEM at once for a request that
+ * needs more than the whole budget. */
+int asj_server_submit(asj_server *s, const uint8_t *data, const int64_t *offsets, int64_t n, asj_pair *out,
+                      int64_t out_cap, int64_t *ticket);
+
+/* Blocks until the request has finished; fills info (may be NULL), releases
+ * the ticket and returns the request's status. */
+int asj_server_wait(asj_server *s, int64_t ticket, asj_request_info *info);
+
+int asj_server_stats(asj_server *s, asj_server_stats_t *stats);
+
+/* Finishes every queued request, then releases the server. */
+int asj_server_destroy(asj_server *s);
+
 /* Waits for the table's build work and returns ASJ_OK or ASJ_ETABLEFULL. */
 int asj_table_status(const asj_table *t);
 

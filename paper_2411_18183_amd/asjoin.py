@@ -308,3 +308,104 @@ def join_batch(R: DeviceKeys, S: DeviceKeys, r_seg_host, s_seg_host, caps=None, 
             break
         caps = np.maximum(caps, c)
     return out, out_seg_host, c, cands.cpu().numpy(), clock.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# serving: probe requests against a resident table
+# ---------------------------------------------------------------------------
+
+class asj_server_opts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64), ("max_batch_keys", ctypes.c_int64),
+                ("max_batch_requests", ctypes.c_int32), ("dry_run", ctypes.c_int32),
+                ("dry_ns_per_key", ctypes.c_double)]
+
+
+class asj_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("count", ctypes.c_int64), ("t_arrive_ms", ctypes.c_double),
+                ("t_launch_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double), ("batch_id", ctypes.c_int32),
+                ("batch_requests", ctypes.c_int32)]
+
+
+class asj_server_stats_t(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("busy_slots", ctypes.c_int64), ("budget_used", ctypes.c_int64),
+                ("peak_budget_used", ctypes.c_int64), ("launches", ctypes.c_int64), ("now_ms", ctypes.c_double)]
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_ready", False):
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        L.asj_server_create.argtypes = [P, ctypes.POINTER(asj_server_opts), ctypes.POINTER(P)]
+        L.asj_server_submit.argtypes = [P, P, P, I64, P, I64, ctypes.POINTER(I64)]
+        L.asj_server_wait.argtypes = [P, I64, ctypes.POINTER(asj_request_info)]
+        L.asj_server_stats.argtypes = [P, ctypes.POINTER(asj_server_stats_t)]
+        L.asj_server_destroy.argtypes = [P]
+        for name in ("asj_server_create", "asj_server_submit", "asj_server_wait", "asj_server_stats",
+                     "asj_server_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        L._server_ready = True
+    return L
+
+
+def _host_ptr(a):
+    """Address of a host buffer: a numpy array or a CPU torch tensor (pinned or not)."""
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda or not a.is_contiguous():
+            raise ValueError("server buffers must be contiguous host tensors")
+        return ctypes.c_void_p(a.data_ptr()) if a.numel() else None
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("server buffers must be contiguous")
+    return ctypes.c_void_p(a.ctypes.data) if a.size else None
+
+
+class Server:
+    """asj_server: continuous-batching probe server over a resident table."""
+
+    def __init__(self, table: Optional[Table], slots: int = 4, hbm_budget: int = 0, max_batch_keys: int = 0,
+                 max_batch_requests: int = 0, dry_run: bool = False, dry_ns_per_key: float = 0.0):
+        L = _server_lib()
+        o = asj_server_opts(slots, int(hbm_budget), int(max_batch_keys), int(max_batch_requests),
+                            1 if dry_run else 0, float(dry_ns_per_key))
+        h = ctypes.c_void_p()
+        _check(L.asj_server_create(table.handle if table is not None else None, ctypes.byref(o), ctypes.byref(h)),
+               "asj_server_create")
+        self.handle = h
+        self.table = table
+        self._live = {}
+
+    def submit(self, data, offsets, out, out_cap: Optional[int] = None) -> int:
+        """Queue a request; data uint8 / offsets int64 / out int32 [cap, 2] host buffers kept alive until wait()."""
+        n = (offsets.numel() if isinstance(offsets, torch.Tensor) else offsets.size) - 1
+        cap = (out.shape[0] if out is not None else 0) if out_cap is None else out_cap
+        t = ctypes.c_int64()
+        _check(_server_lib().asj_server_submit(self.handle, _host_ptr(data), _host_ptr(offsets), n, _host_ptr(out),
+                                               int(cap), ctypes.byref(t)), "asj_server_submit")
+        self._live[t.value] = (data, offsets, out)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        info = asj_request_info()
+        rc = _server_lib().asj_server_wait(self.handle, int(ticket), ctypes.byref(info))
+        self._live.pop(ticket, None)
+        return {"status": rc, "count": int(info.count), "t_arrive_ms": info.t_arrive_ms,
+                "t_launch_ms": info.t_launch_ms, "t_done_ms": info.t_done_ms, "batch_id": info.batch_id,
+                "batch_requests": info.batch_requests}
+
+    def stats(self) -> dict:
+        st = asj_server_stats_t()
+        _check(_server_lib().asj_server_stats(self.handle, ctypes.byref(st)), "asj_server_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(_server_lib().asj_server_destroy(self.handle), "asj_server_destroy")
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,18 +9,6 @@
 
 #include "asj_internal.h"
 
-struct asj_table {
-    asj_keys r;              // borrowed build relation
-    uint64_t *slots;         // capacity slots
-    int64_t capacity;        // power of two
-    int32_t *status;         // device word: 0 or ASJ_ETABLEFULL
-    int plain;               // baseline table (no signature stored)
-    int verify;              // probe compares key bytes of candidates
-    asj_sig_params sig;      // signature parameters of the build
-    hipStream_t stream;      // build stream (orders free)
-    int device;
-};
-
 namespace {
 
 constexpr int kMaxDevices = 64;
@@ -309,6 +297,14 @@ int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *si
 }
 
 } // namespace
+
+const uint16_t *asj_device_tables(int *dev)
+{
+    int d = 0;
+    if (ensure_init(&d) != ASJ_OK) return nullptr;
+    if (dev) *dev = d;
+    return g_dev[d].tab;
+}
 
 extern "C" {
 

@@ -148,6 +148,23 @@ __device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)
     return lo;
 }
 
+// The build-side table (asj_table in the public header).
+struct asj_table {
+    asj_keys r;          // borrowed build relation
+    uint64_t *slots;     // capacity slots
+    int64_t capacity;    // power of two
+    int32_t *status;     // device word: 0 or ASJ_ETABLEFULL
+    int plain;           // baseline table (no signature stored)
+    int verify;          // probe compares key bytes of candidates
+    asj_sig_params sig;  // signature parameters of the build
+    hipStream_t stream;  // build stream (orders free)
+    int device;
+};
+
+// GF constant tables of the current device (initialising the library on
+// first use); nullptr on failure.
+const uint16_t *asj_device_tables(int *dev);
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files; all asynchronous on `st`)
 // ---------------------------------------------------------------------------
