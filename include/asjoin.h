@@ -85,11 +85,15 @@ typedef struct asj_sig_params {
 } asj_sig_params;
 
 /* Join options.  sig = {0, 0} means {16, 2}; load_factor <= 0 means 0.5
- * (table capacity = next power of two >= m / load_factor, at least 64). */
+ * (table capacity = next power of two >= m / load_factor, at least 64);
+ * keys_per_window = probe keys a wave takes at a time, 1..64 (<= 0: the
+ * library's default); it trades lane use in the probe walk against how
+ * soon a probe key is re-read for verification after it was signed. */
 typedef struct asj_opts {
     asj_sig_params sig;
     float load_factor;
     uint32_t flags;
+    int32_t keys_per_window;
 } asj_opts;
 
 /* Opaque build-side hash table H_sign (Section 3.2): an open-addressing
@@ -280,8 +284,14 @@ int asj_timing_enable(int on);
 int asj_timing_read(float *ms, const char **names, int cap);
 
 /* Plain device-to-device copy of `bytes` bytes with the library's own
- * kernel (used to calibrate hardware byte counters against a known size). */
+ * kernel (used to calibrate hardware byte counters against a known size).
+ * dst and src 16-byte aligned. */
 int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t stream);
+
+/* Streaming read of `bytes` bytes (16-byte aligned src) with `grid` blocks of
+ * 256 threads (<= 0: 2048); XORs a fold of the data into *out_word (device).
+ * Measures the achievable read bandwidth that the join kernels are held to. */
+int asj_util_read(const void *src, int64_t bytes, uint32_t *out_word, int grid, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,8 @@ class asj_sig_params(ctypes.Structure):
 
 
 class asj_opts(ctypes.Structure):
-    _fields_ = [("sig", asj_sig_params), ("load_factor", ctypes.c_float), ("flags", ctypes.c_uint32)]
+    _fields_ = [("sig", asj_sig_params), ("load_factor", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("keys_per_window", ctypes.c_int32)]
 
 
 class asj_batch(ctypes.Structure):
@@ -174,14 +175,14 @@ class Table:
             pass
 
 
-def _opts(f, nsym, load_factor, flags) -> asj_opts:
-    return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags))
+def _opts(f, nsym, load_factor, flags, keys_per_window=0) -> asj_opts:
+    return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags), int(keys_per_window))
 
 
 def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.5, flags: int = 0,
-              stream=None) -> Table:
+              keys_per_window: int = 0, stream=None) -> Table:
     k = R.c()
-    o = _opts(f, nsym, load_factor, flags)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window)
     h = ctypes.c_void_p()
     _check(lib().asj_build(ctypes.byref(k), ctypes.byref(o), ctypes.byref(h), _stream(stream)), "asj_build")
     return Table(h, R)
@@ -197,10 +198,10 @@ def asj_probe(t: Table, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, 
 
 
 def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, f: int = 16, nsym: int = 2,
-             load_factor: float = 0.5, flags: int = 0, stream=None):
+             load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0, stream=None):
     """Launch a whole join.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
     kr, ks = R.c(), S.c()
-    o = _opts(f, nsym, load_factor, flags)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window)
     cap = out.shape[0]
     _check(lib().asj_join(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
                           ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.c_void_p(counts.data_ptr()),
@@ -236,6 +237,14 @@ def timing_read(cap: int = 16):
     return [(names[i].decode(), float(ms[i])) for i in range(min(n, cap))]
 
 
+def asj_util_read(src: torch.Tensor, nbytes: int, out_word: torch.Tensor, grid: int = 0, stream=None):
+    L = lib()
+    L.asj_util_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    L.asj_util_read.restype = ctypes.c_int
+    _check(L.asj_util_read(ctypes.c_void_p(src.data_ptr()), int(nbytes), ctypes.c_void_p(out_word.data_ptr()),
+                           int(grid), _stream(stream)), "asj_util_read")
+
+
 def asj_util_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
     _check(lib().asj_util_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes),
                                _stream(stream)), "asj_util_copy")
@@ -261,7 +270,7 @@ def asj_batch_workspace_bytes(njoins: int, n_build: int, f: int = 16, nsym: int 
 def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: torch.Tensor, out: torch.Tensor,
                    out_seg: torch.Tensor, out_count: torch.Tensor, cand_count: Optional[torch.Tensor] = None,
                    done_clock: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None, f: int = 16,
-                   nsym: int = 2, load_factor: float = 0.5, flags: int = 0, stream=None):
+                   nsym: int = 2, load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0, stream=None):
     """Launch a batch of joins (see asj_batch in the header).  All tensors on the device:
     r_seg/s_seg/out_seg int64 [J+1], out int32 [*, 2], out_count (and cand_count) int64 [J],
     done_clock int64 [J+1] (device clock ticks), workspace uint8 (optional)."""
@@ -272,7 +281,7 @@ def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: tor
     b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count),
                   _ptr(cand_count), _ptr(done_clock), _ptr(workspace),
                   int(workspace.numel()) if workspace is not None else 0)
-    o = _opts(f, nsym, load_factor, flags)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window)
     _check(lib().asj_join_batch(ctypes.byref(b), ctypes.byref(o), _stream(stream)), "asj_join_batch")
 
 

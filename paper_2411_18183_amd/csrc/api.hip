@@ -165,6 +165,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->plain = plain;
     t->verify = verify;
     t->sig = sig;
+    t->keys_per_window = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE) ? o.keys_per_window
+                                                                                  : ASJ_DEFAULT_KEYS_PER_WINDOW;
     t->stream = st;
     t->device = dev;
     uint32_t *sig_r = nullptr;
@@ -220,6 +222,8 @@ int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out
     a.rdata = t->r.data;
     a.roff = t->r.offsets;
     a.rids = t->r.ids;
+    a.rn = t->r.n;
+    a.keys_per_window = t->keys_per_window;
     a.sdata = s->data;
     a.soff = s->offsets;
     a.sids = s->ids;
@@ -279,7 +283,7 @@ bool batch_layout(int32_t J, int64_t n_build, float lf, BatchLayout *L)
     return true;
 }
 
-int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf)
+int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf, int *kpw = nullptr)
 {
     asj_opts o = {};
     if (opts) o = *opts;
@@ -293,6 +297,9 @@ int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *si
     }
     *lf = o.load_factor > 0.0f ? o.load_factor : 0.5f;
     if (!(*lf > 0.0f && *lf < 1.0f)) return ASJ_EINVAL;
+    if (kpw)
+        *kpw = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE) ? o.keys_per_window
+                                                                        : ASJ_DEFAULT_KEYS_PER_WINDOW;
     return ASJ_OK;
 }
 
@@ -397,6 +404,18 @@ int asj_timing_read(float *ms, const char **names, int cap)
     return n;
 }
 
+int asj_util_read(const void *src, int64_t bytes, uint32_t *out_word, int grid, hipStream_t st)
+{
+    if (bytes < 0 || (bytes > 0 && (!src || !out_word)) || ((uintptr_t)src & 15u)) return ASJ_EINVAL;
+    if (grid <= 0) grid = 256 * 8;
+    int dev = 0;
+    int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    TimingScope ts;
+    TIMED("read", asj_launch_read(src, bytes, out_word, grid, st));
+    return ASJ_OK;
+}
+
 int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
 {
     if (bytes < 0 || (bytes > 0 && (!dst || !src))) return ASJ_EINVAL;
@@ -427,10 +446,10 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     if (!b || b->njoins < 1 || !keys_ok(&b->r) || !keys_ok(&b->s) || !b->r_seg || !b->s_seg || !b->out_seg ||
         !b->out_count || !b->out)
         return ASJ_EINVAL;
-    int plain, verify;
+    int plain, verify, kpw;
     asj_sig_params sig;
     float lf;
-    int rc = batch_opts(opts, &plain, &verify, &sig, &lf);
+    int rc = batch_opts(opts, &plain, &verify, &sig, &lf, &kpw);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, lf, &L)) return ASJ_EINVAL;
@@ -474,6 +493,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.rdata = b->r.data;
         a.roff = b->r.offsets;
         a.rids = b->r.ids;
+        a.rn = b->r.n;
+        a.keys_per_window = kpw;
         a.sdata = b->s.data;
         a.soff = b->s.offsets;
         a.sids = b->s.ids;

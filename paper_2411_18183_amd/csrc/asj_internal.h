@@ -9,6 +9,7 @@
 #define ASJ_WAVE 64
 #define ASJ_CHUNK 64          // key bytes handled by one lane per pass
 #define ASJ_EMPTY_SLOT (~0ull)
+#define ASJ_DEFAULT_KEYS_PER_WINDOW 64
 
 // ---------------------------------------------------------------------------
 // GF(2^16) constant-multiply tables.
@@ -88,7 +89,7 @@ __device__ inline int asj_wave_incl_scan(int v)
 
 // Chunk loaders.  A key of len bytes is read as floor(len / 64) full 64-byte
 // chunks and, when len is not a multiple of 64, one tail chunk of len % 64
-// bytes.  Both return 16 little-endian words holding key-relative bytes
+// bytes.  The loaders return 16 little-endian words holding key-relative bytes
 // (word t = key bytes k0+4t .. k0+4t+3, where `a` is the arena address of
 // key byte k0).  Only 4-byte-aligned words that hold at least one byte of
 // the key are read, so a load never leaves the pages of the arena.
@@ -157,6 +158,7 @@ struct asj_table {
     int plain;           // baseline table (no signature stored)
     int verify;          // probe compares key bytes of candidates
     asj_sig_params sig;  // signature parameters of the build
+    int keys_per_window; // probe keys per wave window used by probes of this table
     hipStream_t stream;  // build stream (orders free)
     int device;
 };
@@ -206,6 +208,7 @@ struct asj_probe_args {
     const uint8_t *rdata;
     const int64_t *roff;
     const int32_t *rids;
+    int64_t rn; // build rows (roff[rn] is the end of the build arena)
     const uint8_t *sdata;
     const int64_t *soff;
     const int32_t *sids;
@@ -219,6 +222,7 @@ struct asj_probe_args {
     const int32_t *table_status; // device; non-zero means the build failed
     int plain;
     int verify;
+    int keys_per_window; // probe keys per wave window (1..64)
     // batch of joins (njoins > 0): probe row k belongs to join j with
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
     // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its
@@ -234,6 +238,7 @@ struct asj_probe_args {
 hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st);
 hipError_t asj_launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
+hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int grid, hipStream_t st);
 
 // Batch: per-join segment plan (capacities, prefix offsets, counters, start
 // clock), slot initialisation up to the planned total, batched inserts.

@@ -3,7 +3,9 @@
 // (Section 3.2, Figure 2: sign and probe every tuple of S and output the
 // matching tuples; Section 2: matching tuples are concatenated into T).
 //
-// A wave takes a window of 64 probe keys, one key per lane.
+// A wave takes a window of up to 64 probe keys, one key per lane (fewer keys
+// per window make the verification re-read of a key come sooner after its
+// signing read, while the bytes are still in the L2 cache).
 //   1. The window's keys are signed (sign_window.h), so the keys' bytes are
 //      still cache-resident when verification reads them again, and no
 //      signature array goes through memory.
@@ -14,10 +16,12 @@
 //      candidates directly; here each one is compared byte by byte unless
 //      verification is switched off).  The wave advances all walks in rounds
 //      of at most one candidate per lane.
-//   3. A round rejects candidates whose length differs, cuts the remaining
-//      pairs into full 64-byte key-relative chunks laid out back to back
-//      (passes of 64 chunks, one per lane, mismatches flagged in LDS), and
-//      then lets every lane compare its own pair's partial last chunk.
+//   3. A round rejects candidates whose length differs and cuts the
+//      remaining pairs into ceil(len / 64) chunks laid out back to back:
+//      passes of 64 chunks, one per lane, compare both keys and flag
+//      mismatching pairs in LDS.  The last chunk of a key of at least 64
+//      bytes is the key's final 64 bytes (overlapping its neighbour), so
+//      every compared chunk is a full, unguarded, unmasked read.
 //   4. Surviving pairs are appended to the output with one atomic add per
 //      wave and round (ballot + popcount prefix).
 // The baseline simple hash join runs the same kernel with the plain key hash
@@ -97,7 +101,8 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
     __shared__ uint16_t tab[asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];  // probe key starts
     __shared__ int64_t krs[kWaves][ASJ_WAVE];  // candidate build key starts
-    __shared__ int32_t kex[kWaves][ASJ_WAVE];  // exclusive prefix of full-chunk counts
+    __shared__ int32_t kln[kWaves][ASJ_WAVE];  // key lengths
+    __shared__ int32_t kex[kWaves][ASJ_WAVE];  // exclusive prefix of chunk counts
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE]; // signature accumulators, then mismatch flags
 
     if (*a.table_status != 0) { // same value for every thread: the whole grid leaves
@@ -111,14 +116,16 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
     int64_t *wst = kst[wave];
     int64_t *wrs = krs[wave];
+    int32_t *wln = kln[wave];
     int32_t *wex = kex[wave];
     uint32_t *wacc = kacc[wave];
     int64_t wave_cand = 0;
 
-    const int64_t nwin = (a.n + ASJ_WAVE - 1) / ASJ_WAVE;
+    const int kpw = a.keys_per_window;
+    const int64_t nwin = (a.n + kpw - 1) / kpw;
     for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += (int64_t)gridDim.x * kWaves) {
-        const int64_t k = win * ASJ_WAVE + lane;
-        const bool valid = k < a.n;
+        const int64_t k = win * kpw + lane;
+        const bool valid = lane < kpw && k < a.n;
         int64_t ss = 0;
         int ls = 0;
         int32_t sid = 0;
@@ -169,44 +176,44 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
                     lr = (int)((int64_t)o.y - rs);
                 }
                 const bool eq = has && lr == ls;
-                // full 64-byte chunks of every equal-length pair, one per lane
-                const int nfull = eq ? ls / ASJ_CHUNK : 0;
-                const int incl = asj_wave_incl_scan(nfull);
+                // the chunks of every equal-length pair, one per lane
+                const int nch = eq ? (ls + ASJ_CHUNK - 1) / ASJ_CHUNK : 0;
+                const int incl = asj_wave_incl_scan(nch);
                 const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
                 wst[lane] = ss;
                 wrs[lane] = rs;
-                wex[lane] = incl - nfull;
+                wln[lane] = ls;
+                wex[lane] = incl - nch;
                 wacc[lane] = 0;
                 asj_wave_sync();
                 for (int base = 0; base < total; base += ASJ_WAVE) {
                     const int x = base + lane;
                     if (x < total) {
                         const int i = asj_find_owner(wex, x);
-                        const int64_t k0 = (int64_t)(x - wex[i]) * ASJ_CHUNK;
-                        uint32_t kr[16], ks[16];
-                        asj_load_full(a.rdata, wrs[i] + k0, kr);
-                        asj_load_full(a.sdata, wst[i] + k0, ks);
+                        const int c = x - wex[i];
+                        const int L = wln[i];
                         uint32_t diff = 0;
+                        if (L >= ASJ_CHUNK) {
+                            // chunk c covers [64c, 64c + 64); the last one ends at
+                            // the key's end, [L - 64, L), overlapping its neighbour
+                            const int64_t k0 = (c + 1) * ASJ_CHUNK <= L ? (int64_t)c * ASJ_CHUNK : (int64_t)(L - ASJ_CHUNK);
+                            uint32_t kr[16], ks[16];
+                            asj_load_full(a.rdata, wrs[i] + k0, kr);
+                            asj_load_full(a.sdata, wst[i] + k0, ks);
 #pragma unroll
-                        for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                            for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                        } else {
+                            uint32_t kr[16], ks[16];
+                            asj_load_tail(a.rdata, wrs[i], L, kr);
+                            asj_load_tail(a.sdata, wst[i], L, ks);
+#pragma unroll
+                            for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                        }
                         if (diff) wacc[i] = 1u; // every writer stores the same value
                     }
                 }
-                // each lane compares its own pair's last, partial chunk
-                bool tail_ok = true;
-                const int rem = ls - nfull * ASJ_CHUNK;
-                if (eq && rem > 0) {
-                    const int64_t k0 = (int64_t)nfull * ASJ_CHUNK;
-                    uint32_t kr[16], ks[16];
-                    asj_load_tail(a.rdata, rs + k0, rem, kr);
-                    asj_load_tail(a.sdata, ss + k0, rem, ks);
-                    uint32_t diff = 0;
-#pragma unroll
-                    for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
-                    tail_ok = diff == 0;
-                }
                 asj_wave_sync();
-                ok = eq && tail_ok && wacc[lane] == 0u;
+                ok = eq && wacc[lane] == 0u;
                 asj_wave_sync();
             }
             // append the survivors: one atomic per wave, round and join
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
 template <int MODE, int NSYM, int PLAIN, int VERIFY>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
-    const int64_t nwin = (a->n + ASJ_WAVE - 1) / ASJ_WAVE;
+    const int64_t nwin = (a->n + a->keys_per_window - 1) / a->keys_per_window;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
@@ -279,9 +286,12 @@ hipError_t launch_sig(const asj_probe_args *a, const uint16_t *tab, int grid_cap
 
 } // namespace
 
-hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
+hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st)
 {
+    asj_probe_args fixed = *a_in;
+    if (fixed.keys_per_window < 1 || fixed.keys_per_window > ASJ_WAVE) fixed.keys_per_window = ASJ_WAVE;
+    const asj_probe_args *a = &fixed;
     if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch_sig<ASJ_MODE_SIG16, 2>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch_sig<ASJ_MODE_SIG16, 1>(a, tab, grid_cap, st);

@@ -174,6 +174,8 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.rdata = S->tbl.r.data;
         a.roff = S->tbl.r.offsets;
         a.rids = S->tbl.r.ids;
+        a.rn = S->tbl.r.n;
+        a.keys_per_window = S->tbl.keys_per_window;
         a.sdata = d + o_data;
         a.soff = (const int64_t *)(d + o_off);
         a.sids = (const int32_t *)(d + o_sid);
