@@ -140,7 +140,7 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
     r_seg, s_seg, out_seg = dev(bw.r_seg), dev(bw.s_seg), dev(oseg)
     cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
     clock = torch.zeros(J + 1, dtype=torch.int64, device="cuda")
-    ws = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n, bw.S.n), dtype=torch.uint8, device="cuda")
     run = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, clock, workspace=ws)
     for _ in range(max(1, warmup)):
         run()

@@ -172,7 +172,10 @@ int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pai
  *               captured into a HIP graph)
  * Each join gets its own table segment (capacity = next power of two >=
  * |R_j| / load_factor, at least 64).  Errors: ASJ_EINVAL, ASJ_ENOMEM,
- * ASJ_EUNSUPPORTED, ASJ_EHIP. */
+ * ASJ_EUNSUPPORTED, ASJ_EHIP.  The segment arrays are read on the device
+ * only: when they do not cover the relations exactly (r_seg[0] = 0,
+ * r_seg[njoins] = r.n, no bound decreasing; likewise s_seg), or a segment
+ * table fills up, nothing is joined and every out_count[j] is set to -1. */
 typedef struct asj_batch {
     asj_keys r;
     asj_keys s;
@@ -189,8 +192,9 @@ typedef struct asj_batch {
 } asj_batch;
 
 /* Device workspace needed by asj_join_batch for njoins joins over n_build
- * build rows with these options (NULL = defaults); -1 on bad arguments. */
-int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, const asj_opts *opts);
+ * build rows and n_probe probe rows with these options (NULL = defaults);
+ * -1 on bad arguments. */
+int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts);
 
 int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream);
 

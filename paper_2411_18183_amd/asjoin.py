@@ -80,7 +80,7 @@ def lib():
         L.asj_timing_enable.argtypes = [ctypes.c_int]
         L.asj_timing_read.argtypes = [P, P, ctypes.c_int]
         L.asj_util_copy.argtypes = [P, P, I64, P]
-        L.asj_batch_workspace_bytes.argtypes = [ctypes.c_int32, I64, ctypes.POINTER(asj_opts)]
+        L.asj_batch_workspace_bytes.argtypes = [ctypes.c_int32, I64, I64, ctypes.POINTER(asj_opts)]
         L.asj_batch_workspace_bytes.restype = I64
         L.asj_join_batch.argtypes = [ctypes.POINTER(asj_batch), ctypes.POINTER(asj_opts), P]
         L.asj_clock_khz.argtypes = []
@@ -258,10 +258,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
 
 
-def asj_batch_workspace_bytes(njoins: int, n_build: int, f: int = 16, nsym: int = 2, load_factor: float = 0.5,
-                              flags: int = 0) -> int:
-    o = _opts(f, nsym, load_factor, flags)
-    v = lib().asj_batch_workspace_bytes(int(njoins), int(n_build), ctypes.byref(o))
+def asj_batch_workspace_bytes(njoins: int, n_build: int, n_probe: int, f: int = 16, nsym: int = 2,
+                              load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0) -> int:
+    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    v = lib().asj_batch_workspace_bytes(int(njoins), int(n_build), int(n_probe), ctypes.byref(o))
     if v < 0:
         raise AsjError(ASJ_EINVAL, "asj_batch_workspace_bytes")
     return int(v)

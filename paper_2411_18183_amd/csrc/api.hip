@@ -255,26 +255,33 @@ int table_free_impl(asj_table *t)
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
 struct BatchLayout {
-    size_t desc, rows_done, total, status, sig, slots, bytes;
-    int64_t slot_bound;
+    size_t desc, rows_done, tot, status, win_r, win_s, sig, slots, bytes;
+    int64_t slot_bound, win_r_cap, win_s_cap;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool batch_layout(int32_t J, int64_t n_build, float lf, BatchLayout *L)
+bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf, BatchLayout *L)
 {
-    if (J < 1 || n_build < 0 || !(lf > 0.0f && lf < 1.0f)) return false;
+    if (J < 1 || n_build < 0 || n_probe < 0 || kpw < 1 || !(lf > 0.0f && lf < 1.0f)) return false;
     // every segment has capacity 64 or less than 2 |R_j| / lf
     L->slot_bound = 64 * (int64_t)J + (int64_t)(2.0 * (double)n_build / lf) + 1;
+    // sum over joins of ceil(rows_j / w) <= rows / w + J
+    L->win_r_cap = n_build / ASJ_WAVE + J + 1;
+    L->win_s_cap = n_probe / kpw + J + 1;
     size_t off = 0;
     L->desc = off;
     off = align256(off + sizeof(asj_join_desc) * (size_t)J);
     L->rows_done = off;
     off = align256(off + sizeof(int64_t) * (size_t)J);
-    L->total = off;
-    off = align256(off + sizeof(uint64_t));
+    L->tot = off;
+    off = align256(off + 3 * sizeof(uint64_t));
     L->status = off;
     off = align256(off + sizeof(int32_t));
+    L->win_r = off;
+    off = align256(off + sizeof(int32_t) * (size_t)L->win_r_cap);
+    L->win_s = off;
+    off = align256(off + sizeof(int32_t) * (size_t)L->win_s_cap);
     L->sig = off;
     off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->slots = off;
@@ -429,14 +436,14 @@ int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
 }
 
 
-int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, const asj_opts *opts)
+int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts)
 {
-    int plain, verify;
+    int plain, verify, kpw;
     asj_sig_params sig;
     float lf;
-    if (batch_opts(opts, &plain, &verify, &sig, &lf) != ASJ_OK) return -1;
+    if (batch_opts(opts, &plain, &verify, &sig, &lf, &kpw) != ASJ_OK) return -1;
     BatchLayout L;
-    if (!batch_layout(njoins, n_build, lf, &L)) return -1;
+    if (!batch_layout(njoins, n_build, n_probe, kpw, lf, &L)) return -1;
     return (int64_t)L.bytes;
 }
 
@@ -452,7 +459,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int rc = batch_opts(opts, &plain, &verify, &sig, &lf, &kpw);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
-    if (!batch_layout(b->njoins, b->r.n, lf, &L)) return ASJ_EINVAL;
+    if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
     int dev = 0;
     rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
@@ -467,18 +474,21 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     }
     asj_join_desc *desc = (asj_join_desc *)(ws + L.desc);
     int64_t *rows_done = (int64_t *)(ws + L.rows_done);
-    uint64_t *total = (uint64_t *)(ws + L.total);
+    uint64_t *tot = (uint64_t *)(ws + L.tot);
     int32_t *status = (int32_t *)(ws + L.status);
+    int32_t *win_r = (int32_t *)(ws + L.win_r);
+    int32_t *win_s = (int32_t *)(ws + L.win_s);
     uint32_t *sig_r = (uint32_t *)(ws + L.sig);
     uint64_t *slots = (uint64_t *)(ws + L.slots);
     int out_rc = ASJ_OK;
     do {
         hipError_t e;
         tim_begin("batch_plan", st);
-        e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, lf, desc, rows_done, b->out_count, b->cand_count,
-                                  b->done_clock, total, st);
-        if (e == hipSuccess) e = asj_launch_fill_slots(slots, L.slot_bound, total, st);
-        if (e == hipSuccess) e = asj_launch_fill_i32(status, 1, 0, st);
+        e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw, desc,
+                                  rows_done, b->out_count, b->cand_count, b->done_clock, tot, status, st);
+        if (e == hipSuccess)
+            e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->njoins, win_r, L.win_r_cap, win_s,
+                                      L.win_s_cap, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
@@ -486,7 +496,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin("insert", st);
-        e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, b->njoins, desc, slots, status, st);
+        e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, desc, win_r, tot, L.win_r_cap, slots, status, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         asj_probe_args a = {};
@@ -509,6 +519,9 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.njoins = b->njoins;
         a.s_seg = b->s_seg;
         a.desc = desc;
+        a.win_join = win_s;
+        a.nwin = tot + 2;
+        a.nwin_cap = L.win_s_cap;
         a.out_seg = b->out_seg;
         a.rows_done = rows_done;
         a.done_clock = b->done_clock;

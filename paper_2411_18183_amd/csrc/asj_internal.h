@@ -185,24 +185,17 @@ hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
 hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
                              int32_t *status, hipStream_t st);
 
-// Per-join table segment of a batch (written on the device by the plan kernel).
+// Per-join plan of a batch (written on the device by the plan kernel, or by
+// the host for the server).  Rows are cut into windows per join, so that no
+// window spans two joins: join j's build rows form windows wbase_r ..
+// (64 rows each, for the inserts) and its probe rows windows wbase ..
+// (keys_per_window rows each, for the probe kernel).
 struct asj_join_desc {
-    uint64_t tbase; // first slot of the join's segment
-    uint64_t mask;  // segment capacity - 1 (a power of two minus one)
+    uint64_t tbase;  // first slot of the join's segment
+    uint64_t mask;   // segment capacity - 1 (a power of two minus one)
+    int64_t wbase;   // first probe window of the join
+    int64_t wbase_r; // first build window of the join
 };
-
-// Largest j in [0, J) with seg[j] <= k, for a non-decreasing seg[] in device
-// memory (empty segments are skipped because a later equal entry wins).
-__device__ __forceinline__ int asj_find_seg(const int64_t *__restrict__ seg, int J, int64_t k)
-{
-    int lo = 0, hi = J - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg[mid] <= k) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 struct asj_probe_args {
     const uint8_t *rdata;
@@ -226,10 +219,15 @@ struct asj_probe_args {
     // batch of joins (njoins > 0): probe row k belongs to join j with
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
     // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its
-    // counters out_count[j], cand_count[j]
+    // counters out_count[j], cand_count[j].  Window w (w < min(*nwin,
+    // nwin_cap)) holds the rows of join win_join[w] from s_seg[j] + (w -
+    // desc[j].wbase) * keys_per_window on.
     int32_t njoins;
     const int64_t *s_seg;
     const asj_join_desc *desc;
+    const int32_t *win_join;
+    const uint64_t *nwin;
+    int64_t nwin_cap;
     const int64_t *out_seg;
     int64_t *rows_done;   // int64[njoins], zeroed: probe rows finished per join
     uint64_t *done_clock; // uint64[njoins] or NULL
@@ -242,9 +240,15 @@ hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int gr
 
 // Batch: per-join segment plan (capacities, prefix offsets, counters, start
 // clock), slot initialisation up to the planned total, batched inserts.
-hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, float load_factor,
-                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
-                                 uint64_t *done_clock, uint64_t *total_slots, hipStream_t st);
-hipError_t asj_launch_fill_slots(uint64_t *slots, int64_t bound, const uint64_t *total_slots, hipStream_t st);
-hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, int32_t njoins,
-                                   const asj_join_desc *desc, uint64_t *slots, int32_t *status, hipStream_t st);
+// tot[0] = slots of all segments, tot[1] = build windows, tot[2] = probe
+// windows; win_r / win_s map windows to joins.
+hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
+                                 int64_t slot_cap, float load_factor, int keys_per_window, asj_join_desc *desc,
+                                 int64_t *rows_done, int64_t *out_count, int64_t *cand_count, uint64_t *done_clock,
+                                 uint64_t *tot, int32_t *status, hipStream_t st);
+hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
+                                 int32_t njoins, int32_t *win_r, int64_t win_r_cap, int32_t *win_s, int64_t win_s_cap,
+                                 hipStream_t st);
+hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
+                                   const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
+                                   int32_t *status, hipStream_t st);

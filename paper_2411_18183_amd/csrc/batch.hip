@@ -2,75 +2,123 @@
 // segment of one slot array (Build(R_j, H_sign) of Section 3.2, Figure 2),
 // sized on the device so that no host round trip is needed; the probe side
 // of all joins then runs through the fused probe kernel in one launch.
+//
+// Rows are handled in windows that never span two joins (64 build rows per
+// insert window, keys_per_window probe rows per probe window), so every
+// window knows its join from one map entry instead of a search over the
+// segment bounds, and all of a window's bookkeeping goes to one join.
 #include "asj_internal.h"
 
 namespace {
 
 constexpr int kPlanBlock = 1024;
 
+// One block: segment capacities, window counts and their prefix sums,
+// counters zeroed, batch start clock.  Segment arrays that do not cover the
+// relations exactly (first bound 0, last bound the row count, no bound
+// decreasing), or segments that would not fit slot_cap slots, set *status
+// to ASJ_EINVAL so that no later kernel of the batch touches the slots.
 __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *__restrict__ r_seg,
-                                                                const int64_t *__restrict__ s_seg, int32_t J, float lf,
-                                                                asj_join_desc *__restrict__ desc,
+                                                                const int64_t *__restrict__ s_seg, int32_t J,
+                                                                int64_t n_r, int64_t n_s, int64_t slot_cap, float lf,
+                                                                int kpw, asj_join_desc *__restrict__ desc,
                                                                 int64_t *__restrict__ rows_done,
                                                                 int64_t *__restrict__ out_count,
                                                                 int64_t *__restrict__ cand_count,
                                                                 uint64_t *__restrict__ done_clock,
-                                                                uint64_t *__restrict__ total_slots)
+                                                                uint64_t *__restrict__ tot, int32_t *__restrict__ status)
 {
-    __shared__ uint64_t scan[kPlanBlock];
-    __shared__ uint64_t carry;
+    __shared__ uint64_t scan[3][kPlanBlock];
+    __shared__ uint64_t carry[3];
+    __shared__ int bad;
     const uint64_t start = wall_clock64();
     const int tid = threadIdx.x;
-    if (tid == 0) carry = 0;
+    if (tid < 3) carry[tid] = 0;
+    if (tid == 0) bad = (r_seg[0] != 0 || s_seg[0] != 0 || r_seg[J] != n_r || s_seg[J] != n_s);
     __syncthreads();
     for (int base = 0; base < J; base += kPlanBlock) {
         const int j = base + tid;
-        uint64_t cap = 0;
+        uint64_t v[3] = {0, 0, 0};
         if (j < J) {
-            const int64_t nr = r_seg[j + 1] - r_seg[j];
-            cap = 64;
+            if (r_seg[j + 1] < r_seg[j] || s_seg[j + 1] < s_seg[j]) bad = 1;
+            const int64_t nr = max((int64_t)0, r_seg[j + 1] - r_seg[j]);
+            const int64_t ns = max((int64_t)0, s_seg[j + 1] - s_seg[j]);
+            uint64_t cap = 64;
             while ((double)cap * lf < (double)nr) cap <<= 1;
+            v[0] = cap;
+            v[1] = (uint64_t)((nr + ASJ_WAVE - 1) / ASJ_WAVE);
+            v[2] = (uint64_t)((ns + kpw - 1) / kpw);
         }
-        scan[tid] = cap;
+#pragma unroll
+        for (int q = 0; q < 3; q++) scan[q][tid] = v[q];
         __syncthreads();
-        for (int d = 1; d < kPlanBlock; d <<= 1) { // inclusive scan
-            const uint64_t v = tid >= d ? scan[tid - d] : 0;
+        for (int d = 1; d < kPlanBlock; d <<= 1) { // inclusive scans
+            uint64_t add[3];
+#pragma unroll
+            for (int q = 0; q < 3; q++) add[q] = tid >= d ? scan[q][tid - d] : 0;
             __syncthreads();
-            scan[tid] += v;
+#pragma unroll
+            for (int q = 0; q < 3; q++) scan[q][tid] += add[q];
             __syncthreads();
         }
         if (j < J) {
-            desc[j].tbase = carry + scan[tid] - cap;
-            desc[j].mask = cap - 1;
+            desc[j].tbase = carry[0] + scan[0][tid] - v[0];
+            desc[j].mask = v[0] - 1;
+            desc[j].wbase_r = (int64_t)(carry[1] + scan[1][tid] - v[1]);
+            desc[j].wbase = (int64_t)(carry[2] + scan[2][tid] - v[2]);
             rows_done[j] = 0;
             out_count[j] = 0;
             if (cand_count) cand_count[j] = 0;
-            if (done_clock) done_clock[j] = (s_seg[j + 1] == s_seg[j]) ? start : 0;
+            if (done_clock) done_clock[j] = (s_seg[j + 1] <= s_seg[j]) ? start : 0;
         }
         __syncthreads();
-        if (tid == kPlanBlock - 1) carry += scan[kPlanBlock - 1];
+        if (tid < 3) carry[tid] += scan[tid][kPlanBlock - 1];
         __syncthreads();
     }
+    if (tid < 3) tot[tid] = bad ? 0 : carry[tid];
     if (tid == 0) {
-        *total_slots = carry;
         if (done_clock) done_clock[J] = start;
+        *status = (bad || carry[0] > (uint64_t)slot_cap) ? (int32_t)ASJ_EINVAL : (int32_t)ASJ_OK;
     }
 }
 
-__global__ void fill_slots_kernel(uint64_t *__restrict__ slots, int64_t bound, const uint64_t *__restrict__ total)
+// Empty slots up to the planned total, then the window -> join maps (block
+// b writes the windows of joins b, b + gridDim.x, ...).  Every write stays
+// inside the caller's capacities whatever the segment arrays hold.
+__global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap, const uint64_t *__restrict__ tot,
+                                  const asj_join_desc *__restrict__ desc, int32_t J, int32_t *__restrict__ win_r,
+                                  int64_t win_r_cap, int32_t *__restrict__ win_s, int64_t win_s_cap)
 {
-    const int64_t n = min(bound, (int64_t)*total);
+    const int64_t n = min(slot_cap, (int64_t)tot[0]);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         slots[i] = ASJ_EMPTY_SLOT;
+    const int64_t nr = min(win_r_cap, (int64_t)tot[1]);
+    const int64_t ns = min(win_s_cap, (int64_t)tot[2]);
+    for (int j = blockIdx.x; j < J; j += gridDim.x) {
+        const int64_t r0 = desc[j].wbase_r, s0 = desc[j].wbase;
+        const int64_t r1 = j + 1 < J ? desc[j + 1].wbase_r : nr;
+        const int64_t s1 = j + 1 < J ? desc[j + 1].wbase : ns;
+        for (int64_t w = r0 + threadIdx.x; w < min(r1, nr); w += blockDim.x) win_r[w] = j;
+        for (int64_t w = s0 + threadIdx.x; w < min(s1, ns); w += blockDim.x) win_s[w] = j;
+    }
 }
 
+// Lane l of build window w inserts row r_seg[j] + 64 (w - wbase_r) + l of
+// join j = win_r[w] into the join's segment (linear probing, 64-bit CAS).
 __global__ void insert_batch_kernel(const uint32_t *__restrict__ sig, int64_t m, const int64_t *__restrict__ r_seg,
-                                    int32_t J, const asj_join_desc *__restrict__ desc, uint64_t *__restrict__ slots,
+                                    const asj_join_desc *__restrict__ desc, const int32_t *__restrict__ win_r,
+                                    const uint64_t *__restrict__ tot, int64_t win_cap, uint64_t *__restrict__ slots,
                                     int32_t *__restrict__ status)
 {
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m; g += (int64_t)gridDim.x * blockDim.x) {
-        const int j = asj_find_seg(r_seg, J, g);
+    if (*status != ASJ_OK) return; // same value for every thread
+    const int64_t nw = min(win_cap, (int64_t)tot[1]);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nw * ASJ_WAVE;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = t / ASJ_WAVE;
+        const int j = win_r[w];
         const asj_join_desc d = desc[j];
+        const int64_t g = r_seg[j] + (w - d.wbase_r) * ASJ_WAVE + (t % ASJ_WAVE);
+        if (g < 0 || g >= r_seg[j + 1] || g >= m) continue;
         const uint32_t sg = sig[g];
         const uint64_t val = ((uint64_t)sg << 32) | (uint32_t)g;
         uint64_t h = asj_mix32(sg) & d.mask;
@@ -98,28 +146,33 @@ int grid_for(int64_t n, int block, int cap)
 
 } // namespace
 
-hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, float load_factor,
-                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
-                                 uint64_t *done_clock, uint64_t *total_slots, hipStream_t st)
+hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
+                                 int64_t slot_cap, float load_factor, int keys_per_window, asj_join_desc *desc,
+                                 int64_t *rows_done, int64_t *out_count, int64_t *cand_count, uint64_t *done_clock,
+                                 uint64_t *tot, int32_t *status, hipStream_t st)
 {
-    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, load_factor, desc,
-                       rows_done, out_count, cand_count, done_clock, total_slots);
+    if (keys_per_window < 1 || keys_per_window > ASJ_WAVE) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s, slot_cap,
+                       load_factor, keys_per_window, desc, rows_done, out_count, cand_count, done_clock, tot, status);
     return hipGetLastError();
 }
 
-hipError_t asj_launch_fill_slots(uint64_t *slots, int64_t bound, const uint64_t *total_slots, hipStream_t st)
+hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
+                                 int32_t njoins, int32_t *win_r, int64_t win_r_cap, int32_t *win_s, int64_t win_s_cap,
+                                 hipStream_t st)
 {
-    if (bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_slots_kernel, dim3(grid_for(bound, 256, 16384)), dim3(256), 0, st, slots, bound,
-                       total_slots);
+    const int g = grid_for(slot_cap > njoins * 256LL ? slot_cap : njoins * 256LL, 256, 16384);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, slots, slot_cap, tot, desc, njoins, win_r,
+                       win_r_cap, win_s, win_s_cap);
     return hipGetLastError();
 }
 
-hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, int32_t njoins,
-                                   const asj_join_desc *desc, uint64_t *slots, int32_t *status, hipStream_t st)
+hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
+                                   const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
+                                   int32_t *status, hipStream_t st)
 {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(insert_batch_kernel, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, sig, m, r_seg, njoins,
-                       desc, slots, status);
+    if (m <= 0 || win_r_cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(insert_batch_kernel, dim3(grid_for(win_r_cap * ASJ_WAVE, 256, 16384)), dim3(256), 0, st, sig,
+                       m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
     return hipGetLastError();
 }

@@ -28,10 +28,10 @@
 //      cost 11% of the kernel.
 // The baseline simple hash join runs the same kernel with the plain key hash
 // and treats every occupied slot as a candidate (no signature stored).
-// In batch mode every lane finds its join (segment search over the probe
-// rows), probes that join's table segment and appends to that join's output
-// segment; emission then takes one atomic per wave, round and join, and the
-// wave that finishes a join's last probe row stamps its completion clock.
+// In batch mode windows never span two joins: a window reads its join from
+// the window map, probes that join's table segment, appends to that join's
+// output segment, and the wave that finishes a join's last probe row stamps
+// its completion clock.
 #include "sign_window.h"
 
 namespace {
@@ -110,12 +110,16 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
     __shared__ asj_pair kout[kWaves][kStage];   // result pairs staged before one output reservation
 
     if (*a.table_status != 0) { // same value for every thread: the whole grid leaves
-        if (!BATCH && blockIdx.x == 0 && threadIdx.x == 0) *a.out_count = -1;
+        if (blockIdx.x == 0) {
+            if (!BATCH && threadIdx.x == 0) *a.out_count = -1;
+            if (BATCH)
+                for (int j = threadIdx.x; j < a.njoins; j += kBlock) a.out_count[j] = -1;
+        }
         return;
     }
     asj::load_tables<MODE, kBlock>(tab, gtab);
 
-    const int wave = threadIdx.x / ASJ_WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / ASJ_WAVE);
     const int lane = threadIdx.x % ASJ_WAVE;
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
     int64_t *wst = kst[wave];
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
     int64_t wave_cand = 0;
     asj_pair *wout = kout[wave];
     int nstage = 0;     // staged pairs (wave-uniform)
-    int stage_join = 0; // join they belong to (batch mode)
+    int stage_join = 0; // join of the current window (batch mode)
     // reserve output space for the staged pairs with one atomic and copy them out
     auto flush = [&]() {
         if (nstage == 0) return;
@@ -152,27 +156,31 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
     };
 
     const int kpw = a.keys_per_window;
-    const int64_t nwin = (a.n + kpw - 1) / kpw;
+    const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
     for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += (int64_t)gridDim.x * kWaves) {
-        const int64_t k = win * kpw + lane;
-        const bool valid = lane < kpw && k < a.n;
-        int64_t ss = 0;
-        int ls = 0;
-        int32_t sid = 0;
-        // the lane's join and its table segment
+        // the window's rows [k0, k1), its join and table segment
+        int64_t k0 = win * kpw, k1 = a.n;
         int j = 0;
         const uint64_t *slots = a.slots;
         uint64_t mask = a.mask;
+        if (BATCH) {
+            j = __builtin_amdgcn_readfirstlane(a.win_join[win]);
+            const asj_join_desc d = a.desc[j];
+            slots = a.slots + d.tbase;
+            mask = d.mask;
+            k0 = a.s_seg[j] + (win - d.wbase) * kpw;
+            k1 = min(a.s_seg[j + 1], a.n);
+            stage_join = j;
+        }
+        const int64_t k = k0 + lane;
+        const bool valid = lane < kpw && k >= 0 && k < k1;
+        int64_t ss = 0;
+        int ls = 0;
+        int32_t sid = 0;
         if (valid) {
             ss = a.soff[k];
             ls = (int)(a.soff[k + 1] - ss);
             sid = a.sids ? a.sids[k] : (int32_t)k;
-            if (BATCH) {
-                j = asj_find_seg(a.s_seg, a.njoins, k);
-                const asj_join_desc d = a.desc[j];
-                slots = a.slots + d.tbase;
-                mask = d.mask;
-            }
         }
         const uint32_t sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab);
 
@@ -240,45 +248,25 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
                 asj_wave_sync();
             }
             // stage the survivors in LDS; output space is reserved per flush
-            uint64_t pend = __ballot(ok);
-            while (pend) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int lj = __shfl(j, leader, ASJ_WAVE);
-                if (BATCH && lj != stage_join) {
-                    flush();
-                    stage_join = lj;
-                }
-                const bool mine = ok && (!BATCH || j == lj);
-                const uint64_t m = __ballot(mine);
-                if (mine) {
-                    asj_pair p;
-                    p.r_id = a.rids ? a.rids[r] : (int32_t)r;
-                    p.s_id = sid;
-                    wout[nstage + __popcll(m & lanemask_lt)] = p;
-                }
-                nstage += __popcll(m);
-                pend &= ~m;
-                if (nstage > kStage - ASJ_WAVE) flush();
+            const uint64_t m = __ballot(ok);
+            if (ok) {
+                asj_pair p;
+                p.r_id = a.rids ? a.rids[r] : (int32_t)r;
+                p.s_id = sid;
+                wout[nstage + __popcll(m & lanemask_lt)] = p;
             }
+            nstage += __popcll(m);
+            if (nstage > kStage - ASJ_WAVE) flush();
         }
         if (BATCH) {
             flush(); // a join's pairs are all out before its rows are counted done
-            // per-join candidate counts and completion clocks
-            uint64_t pend = __ballot(valid);
-            while (pend) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int lj = __shfl(j, leader, ASJ_WAVE);
-                const bool mine = valid && j == lj;
-                const uint64_t m = __ballot(mine);
-                const int cands = wave_sum(mine ? lane_cand : 0);
-                if (lane == leader) {
-                    if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + lj), (unsigned long long)cands);
-                    const unsigned long long rows = __popcll(m);
-                    const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + lj), rows);
-                    if (a.done_clock && (int64_t)(before + rows) == a.s_seg[lj + 1] - a.s_seg[lj])
-                        a.done_clock[lj] = wall_clock64();
-                }
-                pend &= ~m;
+            const int cands = wave_sum(lane_cand);
+            const unsigned long long rows = __popcll(__ballot(valid));
+            if (lane == 0 && rows) {
+                if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + j), (unsigned long long)cands);
+                const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), rows);
+                if (a.done_clock && (int64_t)(before + rows) == a.s_seg[j + 1] - a.s_seg[j])
+                    a.done_clock[j] = wall_clock64();
             }
         }
     }
@@ -290,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
 template <int MODE, int NSYM, int PLAIN, int VERIFY>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
-    const int64_t nwin = (a->n + a->keys_per_window - 1) / a->keys_per_window;
+    const int64_t nwin = a->njoins > 0 ? a->nwin_cap : (a->n + a->keys_per_window - 1) / a->keys_per_window;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;

@@ -99,7 +99,7 @@ namespace {
 int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
 {
     const int J = (int)batch.size();
-    int64_t K = 0, D = 0, C = 0;
+    int64_t K = 0, D = 0, C = 0, W = 0;
     for (Req *r : batch) {
         K += r->n;
         D += r->off[r->n] - r->off[0];
@@ -109,6 +109,8 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         sl.dry_done = S->now_ms() + S->o.dry_ns_per_key * 1e-6 * (double)K;
         return ASJ_OK;
     }
+    const int kpw = S->tbl.keys_per_window; // 1 .. 64 for every built table
+    for (Req *r : batch) W += (r->n + kpw - 1) / kpw;
     // device layout
     const size_t o_data = 0;
     const size_t o_off = al256(o_data + (size_t)D);
@@ -116,7 +118,9 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     const size_t o_sseg = al256(o_sid + 4 * (size_t)(K > 0 ? K : 1));
     const size_t o_oseg = al256(o_sseg + 8 * (size_t)(J + 1));
     const size_t o_desc = al256(o_oseg + 8 * (size_t)(J + 1));
-    const size_t o_cnt = al256(o_desc + sizeof(asj_join_desc) * (size_t)J);
+    const size_t o_nwin = al256(o_desc + sizeof(asj_join_desc) * (size_t)J);
+    const size_t o_win = al256(o_nwin + 8);
+    const size_t o_cnt = al256(o_win + 4 * (size_t)(W > 0 ? W : 1));
     const size_t o_done = al256(o_cnt + 8 * (size_t)J);
     const size_t o_out = al256(o_done + 8 * (size_t)J);
     const size_t dev_bytes = al256(o_out + 8 * (size_t)(C > 0 ? C : 1));
@@ -137,13 +141,20 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     int64_t *h_sseg = (int64_t *)(meta + (o_sseg - o_off));
     int64_t *h_oseg = (int64_t *)(meta + (o_oseg - o_off));
     asj_join_desc *h_desc = (asj_join_desc *)(meta + (o_desc - o_off));
-    int64_t row = 0, db = 0, ob = 0;
+    uint64_t *h_nwin = (uint64_t *)(meta + (o_nwin - o_off));
+    int32_t *h_win = (int32_t *)(meta + (o_win - o_off));
+    int64_t row = 0, db = 0, ob = 0, wb = 0;
     for (int j = 0; j < J; j++) {
         const Req *r = batch[j];
         h_sseg[j] = row;
         h_oseg[j] = ob;
         h_desc[j].tbase = 0;
         h_desc[j].mask = (uint64_t)S->tbl.capacity - 1;
+        h_desc[j].wbase = wb;
+        h_desc[j].wbase_r = 0;
+        const int64_t nw = (r->n + kpw - 1) / kpw;
+        for (int64_t w = 0; w < nw; w++) h_win[wb + w] = j;
+        wb += nw;
         const int64_t base = r->off[0];
         for (int64_t k = 0; k < r->n; k++) {
             h_off[row + k] = db + (r->off[k] - base);
@@ -156,6 +167,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     h_off[K] = D;
     h_sseg[J] = K;
     h_oseg[J] = C;
+    *h_nwin = (uint64_t)W;
 
     uint8_t *d = nullptr;
     hipError_t e = hipMallocAsync((void **)&d, dev_bytes, sl.st);
@@ -190,6 +202,9 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.njoins = J;
         a.s_seg = (const int64_t *)(d + o_sseg);
         a.desc = (const asj_join_desc *)(d + o_desc);
+        a.win_join = (const int32_t *)(d + o_win);
+        a.nwin = (const uint64_t *)(d + o_nwin);
+        a.nwin_cap = W;
         a.out_seg = (const int64_t *)(d + o_oseg);
         a.rows_done = (int64_t *)(d + o_done);
         a.done_clock = nullptr;

@@ -67,7 +67,7 @@ def test_batch_empty_joins_duplicates_and_caller_workspace(A, oracle, wl):
     caps = np.array([max(1, len(a) * len(b)) for a, b in joins])
     out_seg = np.zeros(J + 1, dtype=np.int64)
     out_seg[1:] = np.cumsum(caps)
-    ws = torch.empty(A.asj_batch_workspace_bytes(J, Rf.n), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(A.asj_batch_workspace_bytes(J, Rf.n, Sf.n), dtype=torch.uint8, device="cuda")
     dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
     out = torch.empty((int(out_seg[-1]), 2), dtype=torch.int32, device="cuda")
     counts = torch.zeros(J, dtype=torch.int64, device="cuda")
@@ -101,3 +101,19 @@ def test_batch_plain_and_paper_literal(A, oracle, wl, flags_name):
             want, _ = oracle.join_signature(w.R, w.S, verify=False)
         assert counts[k] == len(want)
         assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want)
+
+
+@pytest.mark.parametrize("case", ["last_bound", "decreasing"])
+def test_batch_invalid_segments_report_minus_one(A, wl, case):
+    joins = [([b"a", b"b"], [b"a"]), ([b"c"], [b"c", b"d"]), ([b"e"], [b"e"])]
+    Rf, Sf, r_seg, s_seg = flatten(wl, joins)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    bad = r_seg.copy()
+    if case == "last_bound":
+        bad[-1] += 5  # does not end at the last build row
+    else:
+        bad[1], bad[2] = bad[2], bad[1]  # a segment of negative size
+    _, _, counts, _, _ = A.join_batch(R, S, bad, s_seg)
+    assert (counts == -1).all()
+    _, _, counts, _, _ = A.join_batch(R, S, r_seg, s_seg)  # the same inputs with valid segments
+    assert counts.tolist() == [1, 1, 1]
