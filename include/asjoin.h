@@ -56,6 +56,13 @@ extern "C" {
 #define ASJ_PLAIN 0x2u     /* baseline simple hash join (Section 2): a full-key multiplicative
                               hash instead of the signature; every occupied slot on the probe
                               path is compared by length and bytes (no stored fingerprint) */
+#define ASJ_PROBE_FUSED 0x4u /* probe schedule: each probe key is signed inside the probe kernel,
+                                right before its table walk and verification */
+#define ASJ_PROBE_SPLIT 0x8u /* probe schedule: the probe keys are signed by the signature kernel
+                                into a device scratch array first (4 bytes per key), then a probe
+                                kernel without signing walks and verifies.  Neither flag means
+                                ASJ_PROBE_FUSED; both flags: ASJ_EINVAL.  The output is the
+                                same either way. */
 
 /* A relation's join attributes: key k is data[offsets[k] .. offsets[k+1]).
  * offsets must be non-decreasing (k = 0..n).  The library reads only

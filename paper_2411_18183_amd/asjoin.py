@@ -27,6 +27,8 @@ ASJ_EUNSUPPORTED = -6
 
 ASJ_NO_VERIFY = 0x1
 ASJ_PLAIN = 0x2
+ASJ_PROBE_FUSED = 0x4
+ASJ_PROBE_SPLIT = 0x8
 
 
 class AsjError(RuntimeError):

@@ -120,6 +120,16 @@ int resolve_sig(asj_sig_params p, asj_sig_params *out)
     return ASJ_EUNSUPPORTED;
 }
 
+// Probe schedule from the flags: 1 = split (sign kernel, then a probe
+// kernel with the stored signatures), 0 = fused; -1 = contradictory flags.
+int probe_split(uint32_t flags)
+{
+    const bool fused = (flags & ASJ_PROBE_FUSED) != 0, split = (flags & ASJ_PROBE_SPLIT) != 0;
+    if (fused && split) return -1;
+    if (split) return 1;
+    return 0; // default schedule: fused (faster on every measured workload)
+}
+
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
                            hipStream_t st)
 {
@@ -144,6 +154,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     const int plain = (o.flags & ASJ_PLAIN) != 0;
     const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (plain && !verify) return ASJ_EINVAL; // the plain table has no signature to trust
+    const int split = probe_split(o.flags);
+    if (split < 0) return ASJ_EINVAL;
     asj_sig_params sig = {16, 2};
     if (!plain) {
         int rc = resolve_sig(o.sig, &sig);
@@ -167,6 +179,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->sig = sig;
     t->keys_per_window = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE) ? o.keys_per_window
                                                                                   : ASJ_DEFAULT_KEYS_PER_WINDOW;
+    t->split = split;
     t->stream = st;
     t->device = dev;
     uint32_t *sig_r = nullptr;
@@ -238,9 +251,25 @@ int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out
     a.plain = t->plain;
     a.verify = t->verify;
     const int mode = t->plain ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
-    tim_begin(t->plain ? "hash_probe_verify" : "sign_probe_verify", st);
-    e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+    if (!t->split || s->n == 0) {
+        tim_begin(t->plain ? "hash_probe_verify" : "sign_probe_verify", st);
+        e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        tim_end(st);
+        return e == hipSuccess ? ASJ_OK : hip_fail(e);
+    }
+    uint32_t *ssig = nullptr;
+    e = alloc_async(&ssig, (size_t)s->n, st);
+    if (e != hipSuccess) return hip_fail(e);
+    tim_begin(t->plain ? "hash_S" : "sign_S", st);
+    e = launch_sign_for(s, t->sig, t->plain, ssig, g_dev[dev].tab, st);
     tim_end(st);
+    if (e == hipSuccess) {
+        a.ssig = ssig;
+        tim_begin(t->plain ? "hash_probe_verify" : "probe_verify", st);
+        e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        tim_end(st);
+    }
+    (void)hipFreeAsync(ssig, st);
     return e == hipSuccess ? ASJ_OK : hip_fail(e);
 }
 
@@ -255,7 +284,7 @@ int table_free_impl(asj_table *t)
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
 struct BatchLayout {
-    size_t desc, rows_done, tot, status, win_r, win_s, sig, slots, bytes;
+    size_t desc, rows_done, tot, status, win_r, win_s, sig, ssig, slots, bytes;
     int64_t slot_bound, win_r_cap, win_s_cap;
 };
 
@@ -284,19 +313,25 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     off = align256(off + sizeof(int32_t) * (size_t)L->win_s_cap);
     L->sig = off;
     off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
+    L->ssig = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)(n_probe > 0 ? n_probe : 1));
     L->slots = off;
     off = align256(off + sizeof(uint64_t) * (size_t)L->slot_bound);
     L->bytes = off;
     return true;
 }
 
-int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf, int *kpw = nullptr)
+int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf, int *kpw = nullptr,
+               int *split = nullptr)
 {
     asj_opts o = {};
     if (opts) o = *opts;
     *plain = (o.flags & ASJ_PLAIN) != 0;
     *verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (*plain && !*verify) return ASJ_EINVAL;
+    const int sp = probe_split(o.flags);
+    if (sp < 0) return ASJ_EINVAL;
+    if (split) *split = sp;
     *sig = asj_sig_params{16, 2};
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);
@@ -453,10 +488,10 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     if (!b || b->njoins < 1 || !keys_ok(&b->r) || !keys_ok(&b->s) || !b->r_seg || !b->s_seg || !b->out_seg ||
         !b->out_count || !b->out)
         return ASJ_EINVAL;
-    int plain, verify, kpw;
+    int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int rc = batch_opts(opts, &plain, &verify, &sig, &lf, &kpw);
+    int rc = batch_opts(opts, &plain, &verify, &sig, &lf, &kpw, &split);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
@@ -479,6 +514,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int32_t *win_r = (int32_t *)(ws + L.win_r);
     int32_t *win_s = (int32_t *)(ws + L.win_s);
     uint32_t *sig_r = (uint32_t *)(ws + L.sig);
+    uint32_t *sig_s = (uint32_t *)(ws + L.ssig);
     uint64_t *slots = (uint64_t *)(ws + L.slots);
     int out_rc = ASJ_OK;
     do {
@@ -526,7 +562,14 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.rows_done = rows_done;
         a.done_clock = b->done_clock;
         const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
-        tim_begin(plain ? "hash_probe_verify" : "sign_probe_verify", st);
+        if (split && b->s.n > 0) {
+            tim_begin(plain ? "hash_S" : "sign_S", st);
+            e = launch_sign_for(&b->s, sig, plain, sig_s, g_dev[dev].tab, st);
+            tim_end(st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+            a.ssig = sig_s;
+        }
+        tim_begin(plain ? "hash_probe_verify" : (a.ssig ? "probe_verify" : "sign_probe_verify"), st);
         e = asj_launch_probe(&a, mode, sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }

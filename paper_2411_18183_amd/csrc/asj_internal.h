@@ -96,25 +96,42 @@ __device__ inline int asj_wave_incl_scan(int v)
 
 // Full chunk: the 64 bytes at a are all key bytes.  Words are read at
 // a & ~3 and realigned; the 17th word (needed when a is not 4-aligned)
-// still starts before the key's end.
-__device__ __forceinline__ void asj_load_full(const uint8_t *__restrict__ data, int64_t a, uint32_t kd[16])
-{
-    const uint32_t sh = (uint32_t)(a & 3);
-    const uint32_t *p = (const uint32_t *)(data + (a - sh));
-    const asj_u32x4 *q = (const asj_u32x4 *)p;
+// still starts before the key's end.  Fetching (issuing the loads) and
+// realigning are separate steps so that a caller can have the loads of the
+// next chunk in flight while it folds the current one.
+struct asj_raw_chunk {
     uint32_t d[17];
+    uint32_t sh;
+};
+
+__device__ __forceinline__ void asj_fetch_full(const uint8_t *__restrict__ data, int64_t a, asj_raw_chunk &r)
+{
+    r.sh = (uint32_t)(a & 3);
+    const uint32_t *p = (const uint32_t *)(data + (a - r.sh));
+    const asj_u32x4 *q = (const asj_u32x4 *)p;
 #pragma unroll
     for (int t = 0; t < 4; t++) {
         const asj_u32x4 v = q[t];
-        d[4 * t + 0] = v.x;
-        d[4 * t + 1] = v.y;
-        d[4 * t + 2] = v.z;
-        d[4 * t + 3] = v.w;
+        r.d[4 * t + 0] = v.x;
+        r.d[4 * t + 1] = v.y;
+        r.d[4 * t + 2] = v.z;
+        r.d[4 * t + 3] = v.w;
     }
-    d[16] = 0u;
-    if (sh) d[16] = p[16];
+    r.d[16] = 0u;
+    if (r.sh) r.d[16] = p[16];
+}
+
+__device__ __forceinline__ void asj_align_full(const asj_raw_chunk &r, uint32_t kd[16])
+{
 #pragma unroll
-    for (int t = 0; t < 16; t++) kd[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], sh);
+    for (int t = 0; t < 16; t++) kd[t] = __builtin_amdgcn_alignbyte(r.d[t + 1], r.d[t], r.sh);
+}
+
+__device__ __forceinline__ void asj_load_full(const uint8_t *__restrict__ data, int64_t a, uint32_t kd[16])
+{
+    asj_raw_chunk r;
+    asj_fetch_full(data, a, r);
+    asj_align_full(r, kd);
 }
 
 // Tail chunk: rem (1..63) key bytes at a; bytes at or past rem read as zero.
@@ -159,6 +176,7 @@ struct asj_table {
     int verify;          // probe compares key bytes of candidates
     asj_sig_params sig;  // signature parameters of the build
     int keys_per_window; // probe keys per wave window used by probes of this table
+    int split;           // probes sign the probe keys in a separate kernel first
     hipStream_t stream;  // build stream (orders free)
     int device;
 };
@@ -206,6 +224,7 @@ struct asj_probe_args {
     const int64_t *soff;
     const int32_t *sids;
     int64_t n;
+    const uint32_t *ssig; // signatures (plain hashes) of the probe keys, or NULL to sign them in the kernel
     const uint64_t *slots;
     uint64_t mask;
     asj_pair *out;

@@ -36,8 +36,14 @@
 
 namespace {
 
-constexpr int kBlock = 512;
-constexpr int kWaves = kBlock / ASJ_WAVE;
+// Block size: 8 waves when the kernel signs (one copy of the GF tables in
+// LDS serves more waves), 4 waves when the signatures are given (no tables;
+// the smaller block fits the register-limited wave count per CU exactly).
+template <int PRESIGNED>
+struct Shape {
+    static constexpr int block = PRESIGNED ? 256 : 512;
+    static constexpr int waves = block / ASJ_WAVE;
+};
 constexpr int kStage = 256; // staged result pairs per wave; flushed once more than kStage - 64 wait
 
 typedef uint64_t asj_u64x2 __attribute__((ext_vector_type(2), aligned(16)));
@@ -98,10 +104,13 @@ __device__ __forceinline__ int wave_sum(int v)
     return v;
 }
 
-template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH>
-__global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const uint16_t *__restrict__ gtab)
+template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH, int PRESIGNED>
+__global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_probe_args a,
+                                                                         const uint16_t *__restrict__ gtab)
 {
-    __shared__ uint16_t tab[asj::TabWords<MODE>::value];
+    constexpr int kBlock = Shape<PRESIGNED>::block;
+    constexpr int kWaves = Shape<PRESIGNED>::waves;
+    __shared__ uint16_t tab[PRESIGNED ? 2 : asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];  // probe key starts
     __shared__ int64_t krs[kWaves][ASJ_WAVE];  // candidate build key starts
     __shared__ int32_t kln[kWaves][ASJ_WAVE];  // key lengths
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
         }
         return;
     }
-    asj::load_tables<MODE, kBlock>(tab, gtab);
+    if (!PRESIGNED) asj::load_tables<MODE, kBlock>(tab, gtab);
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / ASJ_WAVE);
     const int lane = threadIdx.x % ASJ_WAVE;
@@ -182,7 +191,12 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
             ls = (int)(a.soff[k + 1] - ss);
             sid = a.sids ? a.sids[k] : (int32_t)k;
         }
-        const uint32_t sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab);
+        uint32_t sg = 0;
+        if (PRESIGNED) {
+            if (valid) sg = a.ssig[k];
+        } else {
+            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab);
+        }
 
         Walk wk;
         wk.h = asj_mix32(sg) & mask;
@@ -275,26 +289,29 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(asj_probe_args a, const u
         atomicAdd((unsigned long long *)a.cand_count, (unsigned long long)wave_cand);
 }
 
-template <int MODE, int NSYM, int PLAIN, int VERIFY>
+template <int MODE, int NSYM, int PLAIN, int VERIFY, int PRESIGNED>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
     const int64_t nwin = a->njoins > 0 ? a->nwin_cap : (a->n + a->keys_per_window - 1) / a->keys_per_window;
+    constexpr int kBlock = Shape<PRESIGNED>::block;
+    constexpr int kWaves = Shape<PRESIGNED>::waves;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
     if (a->njoins > 0)
-        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           *a, tab);
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, *a, tab);
     else
-        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           *a, tab);
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, *a, tab);
     return hipGetLastError();
 }
 
 template <int MODE, int NSYM>
 hipError_t launch_sig(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
-    return a->verify ? launch<MODE, NSYM, 0, 1>(a, tab, grid_cap, st) : launch<MODE, NSYM, 0, 0>(a, tab, grid_cap, st);
+    return a->verify ? launch<MODE, NSYM, 0, 1, 0>(a, tab, grid_cap, st)
+                     : launch<MODE, NSYM, 0, 0, 0>(a, tab, grid_cap, st);
 }
 
 } // namespace
@@ -305,7 +322,12 @@ hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, cons
     asj_probe_args fixed = *a_in;
     if (fixed.keys_per_window < 1 || fixed.keys_per_window > ASJ_WAVE) fixed.keys_per_window = ASJ_WAVE;
     const asj_probe_args *a = &fixed;
-    if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1>(a, tab, grid_cap, st);
+    if (a->ssig) { // signatures (or plain hashes) of the probe keys are given: no signing, no tables
+        if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1, 1>(a, tab, grid_cap, st);
+        return a->verify ? launch<ASJ_MODE_SIG16, 2, 0, 1, 1>(a, tab, grid_cap, st)
+                         : launch<ASJ_MODE_SIG16, 2, 0, 0, 1>(a, tab, grid_cap, st);
+    }
+    if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1, 0>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch_sig<ASJ_MODE_SIG16, 2>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch_sig<ASJ_MODE_SIG16, 1>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch_sig<ASJ_MODE_SIG8, 4>(a, tab, grid_cap, st);

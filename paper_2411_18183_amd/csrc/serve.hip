@@ -62,11 +62,14 @@ struct Slot {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Device bytes one request holds while in flight.
-int64_t request_bytes(int64_t n, int64_t data_bytes, int64_t cap)
+// Device bytes one request holds while in flight: its keys and offsets,
+// probe ids, probe signatures (split schedule), probe windows (kpw keys
+// each), output pairs, and its share of the per-batch segment, descriptor
+// and counter arrays with their alignment.
+int64_t request_bytes(int64_t n, int64_t data_bytes, int64_t cap, int kpw)
 {
-    return (int64_t)(al256((size_t)data_bytes) + al256(8 * (size_t)(n + 1)) + al256(4 * (size_t)n) +
-                     al256(8 * (size_t)cap) + 256 /* segment, descriptor and counter entries */);
+    return (int64_t)(al256((size_t)data_bytes) + al256(8 * (size_t)(n + 1)) + 2 * al256(4 * (size_t)n) +
+                     al256(4 * (size_t)(n / kpw + 1)) + al256(8 * (size_t)cap) + 2048);
 }
 
 } // namespace
@@ -123,7 +126,8 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     const size_t o_cnt = al256(o_win + 4 * (size_t)(W > 0 ? W : 1));
     const size_t o_done = al256(o_cnt + 8 * (size_t)J);
     const size_t o_out = al256(o_done + 8 * (size_t)J);
-    const size_t dev_bytes = al256(o_out + 8 * (size_t)(C > 0 ? C : 1));
+    const size_t o_ssig = al256(o_out + 8 * (size_t)(C > 0 ? C : 1)); // probe signatures (split schedule)
+    const size_t dev_bytes = S->tbl.split ? al256(o_ssig + 4 * (size_t)(K > 0 ? K : 1)) : o_ssig;
     const size_t meta_bytes = o_cnt - o_off; // offsets .. descriptors, staged in one copy
     // pinned staging (metadata, then the counts read back)
     const size_t need = al256(meta_bytes) + al256(8 * (size_t)J);
@@ -209,7 +213,13 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.rows_done = (int64_t *)(d + o_done);
         a.done_clock = nullptr;
         const int mode = S->tbl.plain ? ASJ_MODE_PLAIN : (S->tbl.sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
-        e = asj_launch_probe(&a, mode, S->tbl.sig.nsym, S->tab, 256 * 16, sl.st);
+        if (S->tbl.split && K > 0) {
+            const asj_keys keys = {a.sdata, a.soff, a.sids, K};
+            e = asj_launch_sign(mode, S->tbl.plain ? 1 : S->tbl.sig.nsym, &keys, (uint32_t *)(d + o_ssig), S->tab,
+                                256 * 16, sl.st);
+            a.ssig = (const uint32_t *)(d + o_ssig);
+        }
+        if (e == hipSuccess) e = asj_launch_probe(&a, mode, S->tbl.sig.nsym, S->tab, 256 * 16, sl.st);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.pin + sl.counts_off, d + o_cnt, 8 * (size_t)J, hipMemcpyDeviceToHost, sl.st);
@@ -380,7 +390,8 @@ int asj_server_submit(asj_server *S, const uint8_t *data, const int64_t *offsets
     r->n = n;
     r->out = out;
     r->cap = out_cap;
-    r->bytes = request_bytes(n, data_bytes, out_cap);
+    r->bytes = request_bytes(n, data_bytes, out_cap, S->tbl.keys_per_window >= 1 ? S->tbl.keys_per_window
+                                                                                   : ASJ_DEFAULT_KEYS_PER_WINDOW);
     std::lock_guard<std::mutex> lk(S->mu);
     if (r->bytes > S->o.hbm_budget) {
         delete r;

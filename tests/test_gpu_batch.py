@@ -33,10 +33,14 @@ def flatten(wl, joins):
     return wl.from_keys(rk, rid), wl.from_keys(sk, sid), np.array(r_seg), np.array(s_seg)
 
 
-def test_batch_matches_oracle_and_single_joins(A, oracle, wl):
+SCHED = {"split": 0x8, "fused": 0x4}
+
+
+@pytest.mark.parametrize("sched", sorted(SCHED))
+def test_batch_matches_oracle_and_single_joins(A, oracle, wl, sched):
     b = wl.batch(scale=0.003, njoins=20)
     R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
-    out, oseg, counts, cands, clock = A.join_batch(R, S, b.r_seg, b.s_seg)
+    out, oseg, counts, cands, clock = A.join_batch(R, S, b.r_seg, b.s_seg, flags=SCHED[sched])
     outh = out.cpu().numpy()
     for k in range(b.njoins):
         j = b.join(k)
@@ -84,14 +88,15 @@ def test_batch_empty_joins_duplicates_and_caller_workspace(A, oracle, wl):
             assert np.array_equal(oracle.sort_pairs(outh[out_seg[k]:out_seg[k] + c[k]]), want), (rep, k)
 
 
+@pytest.mark.parametrize("sched", sorted(SCHED))
 @pytest.mark.parametrize("flags_name", ["ASJ_PLAIN", "ASJ_NO_VERIFY"])
-def test_batch_plain_and_paper_literal(A, oracle, wl, flags_name):
+def test_batch_plain_and_paper_literal(A, oracle, wl, flags_name, sched):
     joins = [wl.random_small(s, m=60 + 9 * s, n=80 + 5 * s, max_len=[3, 12, 40][s % 3], alphabet=b"ab\x00")
              for s in range(8)]
     Rf, Sf, r_seg, s_seg = flatten(wl, [([w.R.key(i) for i in range(w.R.n)], [w.S.key(i) for i in range(w.S.n)])
                                         for w in joins])
     R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
-    flags = getattr(A, flags_name)
+    flags = getattr(A, flags_name) | SCHED[sched]
     out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg, flags=flags)
     outh = out.cpu().numpy()
     for k, w in enumerate(joins):

@@ -26,7 +26,16 @@ def gpu_sigs(A, rel, f=16, nsym=2):
     return out.cpu().numpy().view(np.uint32).astype(np.uint64)
 
 
-def gpu_join(A, R, S, **kw):
+SCHEDULES = ["split", "fused"]
+
+
+def sched_flag(A, sched):
+    return {"split": A.ASJ_PROBE_SPLIT, "fused": A.ASJ_PROBE_FUSED}[sched]
+
+
+def gpu_join(A, R, S, sched=None, **kw):
+    if sched is not None:
+        kw["flags"] = kw.get("flags", 0) | sched_flag(A, sched)
     Rk, Sk = A.DeviceKeys.from_host(R), A.DeviceKeys.from_host(S)
     pairs, total, ncand = A.join(Rk, Sk, **kw)
     return pairs.cpu().numpy(), total, ncand
@@ -80,8 +89,9 @@ def test_signature_many_windows_and_ragged_tail(A, oracle, wl):
     assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seed", range(10))
-def test_join_small_random(A, oracle, wl, seed):
+def test_join_small_random(A, oracle, wl, seed, sched):
     alphabets = [b"ab\x00", b"a", b"\x00", bytes(range(256)), b"xy"]
     w = wl.random_small(seed, m=int(50 + 37 * seed), n=int(70 + 53 * seed), max_len=[1, 3, 9, 40, 300][seed % 5],
                         alphabet=alphabets[seed % 5])
@@ -90,17 +100,18 @@ def test_join_small_random(A, oracle, wl, seed):
         w.S.ids = (np.random.default_rng(seed + 1).permutation(w.S.n) + 7000).astype(np.int32)
     want = oracle.join_nested(w.R, w.S)
     _, want_cand = oracle.join_signature(w.R, w.S)
-    got, total, ncand = gpu_join(A, w.R, w.S)
+    got, total, ncand = gpu_join(A, w.R, w.S, sched=sched)
     assert total == len(want)
     assert np.array_equal(oracle.sort_pairs(got), want)
     assert ncand == want_cand
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("name,scale", [("tiny", 1.0), ("large", 0.02), ("dna", 0.01)])
-def test_join_workloads(A, oracle, wl, name, scale):
+def test_join_workloads(A, oracle, wl, name, scale, sched):
     w = getattr(wl, name)(scale=scale)
     want, want_cand = oracle.join_signature(w.R, w.S)
-    got, total, ncand = gpu_join(A, w.R, w.S)
+    got, total, ncand = gpu_join(A, w.R, w.S, sched=sched)
     assert total == len(want) == w.meta["expected_matches"]
     assert np.array_equal(oracle.sort_pairs(got), want)
     assert ncand == want_cand
@@ -117,41 +128,45 @@ def test_join_batch_members(A, oracle, wl):
         assert ncand == want_cand
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seed", range(4))
-def test_plain_baseline_join(A, oracle, wl, seed):
+def test_plain_baseline_join(A, oracle, wl, seed, sched):
     w = wl.random_small(seed, m=300, n=500, max_len=[2, 9, 80, 700][seed], alphabet=b"ab\x00")
-    got, total, _ = gpu_join(A, w.R, w.S, flags=A.ASJ_PLAIN)
+    got, total, _ = gpu_join(A, w.R, w.S, sched=sched, flags=A.ASJ_PLAIN)
     want = oracle.join_nested(w.R, w.S)
     assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)
     t = wl.tiny(scale=0.5)
-    got, total, _ = gpu_join(A, t.R, t.S, flags=A.ASJ_PLAIN)
+    got, total, _ = gpu_join(A, t.R, t.S, sched=sched, flags=A.ASJ_PLAIN)
     assert np.array_equal(oracle.sort_pairs(got), oracle.join_hash(t.R, t.S))
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seed", range(4))
-def test_paper_literal_no_verify(A, oracle, wl, seed):
+def test_paper_literal_no_verify(A, oracle, wl, seed, sched):
     w = wl.random_small(seed, m=200, n=300, max_len=[2, 6, 30, 3][seed], alphabet=b"a\x00")
     want, want_cand = oracle.join_signature(w.R, w.S, verify=False)
-    got, total, ncand = gpu_join(A, w.R, w.S, flags=A.ASJ_NO_VERIFY)
+    got, total, ncand = gpu_join(A, w.R, w.S, sched=sched, flags=A.ASJ_NO_VERIFY)
     assert total == len(want) == ncand == want_cand
     assert np.array_equal(oracle.sort_pairs(got), want)
 
 
-def test_variant_signature_joins(A, oracle, wl):
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_variant_signature_joins(A, oracle, wl, sched):
     w = wl.random_small(3, m=400, n=600, max_len=50, alphabet=b"ab\x00")
     for f, nsym in ((16, 1), (8, 4), (8, 2)):
         want, want_cand = oracle.join_signature(w.R, w.S, f=f, nsym=nsym)
-        got, total, ncand = gpu_join(A, w.R, w.S, f=f, nsym=nsym)
+        got, total, ncand = gpu_join(A, w.R, w.S, sched=sched, f=f, nsym=nsym)
         assert np.array_equal(oracle.sort_pairs(got), want)
         assert ncand == want_cand
 
 
-def test_duplicate_keys_multimap(A, oracle, wl):
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_duplicate_keys_multimap(A, oracle, wl, sched):
     keys_r = [b"k" * 100] * 150 + [b"x" * 7] * 3 + [b""] * 4 + [bytes([i % 7]) * (i % 300) for i in range(500)]
     keys_s = [b"k" * 100] * 40 + [b""] * 5 + [b"x" * 7] + [bytes([i % 5]) * (i % 200) for i in range(700)]
     R, S = wl.from_keys(keys_r), wl.from_keys(keys_s)
     want = oracle.join_hash(R, S)
-    got, total, _ = gpu_join(A, R, S, cap=10)  # forces the second call
+    got, total, _ = gpu_join(A, R, S, sched=sched, cap=10)  # forces the second call
     assert total == len(want) >= 150 * 40
     assert np.array_equal(oracle.sort_pairs(got), want)
 
@@ -220,3 +235,9 @@ def test_rejects_bad_parameters(A, wl):
         A.asj_build(rel, load_factor=1.5)
     with pytest.raises(A.AsjError):
         A.asj_build(rel, flags=A.ASJ_PLAIN | A.ASJ_NO_VERIFY)
+
+
+def test_contradictory_schedule_flags_rejected(A, wl):
+    w = wl.random_small(1, m=10, n=10)
+    with pytest.raises(A.AsjError):
+        gpu_join(A, w.R, w.S, flags=A.ASJ_PROBE_FUSED | A.ASJ_PROBE_SPLIT)

@@ -16,11 +16,12 @@ def A():
     return A
 
 
-def test_results_identical_alone_and_in_the_mix(A, oracle, wl):
+@pytest.mark.parametrize("sched", ["split", "fused"])
+def test_results_identical_alone_and_in_the_mix(A, oracle, wl, sched):
     import torch
     R = wl.served_build_side(scale=0.01)  # 100k resident keys of 256 bytes
     Rk = A.DeviceKeys.from_host(R)
-    t = A.asj_build(Rk)
+    t = A.asj_build(Rk, flags=A.ASJ_PROBE_SPLIT if sched == "split" else A.ASJ_PROBE_FUSED)
     reqs = [wl.served_request(R, seed=5, request=i, min_size=500, max_size=20000) for i in range(10)]
     want = [oracle.join_hash(R, q) for q in reqs]
 
