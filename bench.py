@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="size of the resident build side of the serving run (1.0 = 10M keys; 0 = skip)")
     ap.add_argument("--serve-arrivals", type=int, default=48)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library defaults instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run the library's copy kernel over BYTES bytes (counter calibration)")
     return ap.parse_args()
@@ -136,7 +138,7 @@ def tiny_instances(W, count: int, seed0: int = 1):
     return W.BatchWorkload(f"tiny x{count}", R, S, r_seg, s_seg, {"seed0": seed0})
 
 
-def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
+def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autotune: bool = True):
     """Batched launch sequence vs one asj_join per join, on the same inputs."""
     import numpy as np
     J = bw.njoins
@@ -145,6 +147,9 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
     out, oseg, counts, cands, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg)
     dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
     r_seg, s_seg, out_seg = dev(bw.r_seg), dev(bw.s_seg), dev(oseg)
+    tune = None
+    if autotune:  # setup, not timed; the timed calls leave the options to the library
+        tune = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"))
     cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
     clock = torch.zeros(J + 1, dtype=torch.int64, device="cuda")
     ws = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n, bw.S.n), dtype=torch.uint8, device="cuda")
@@ -217,6 +222,7 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True):
         "join_latency_ms_unbatched": {"p50": round(float(np.percentile(lat_unb, 50)), 4),
                                       "p99": round(float(np.percentile(lat_unb, 99)), 4)},
         "unbatched_counts_match": bool(ok),
+        "autotune": tune,
     }
 
 
@@ -331,6 +337,12 @@ def main():
     out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
     counts = torch.zeros(2, dtype=torch.int64, device="cuda")
 
+    # the autotuner times whole joins over its grid on these inputs (setup, not
+    # timed); the timed joins leave the options to the library, which uses its choice
+    tune = None if args.no_autotune else A.autotune(Rk, Sk, out, counts)
+    if tune:
+        log(f"autotune: {tune}")
+    lf = tune["load_factor"] if tune else 0.5
     # warmup (and the size of T)
     for _ in range(max(1, args.warmup)):
         A.asj_join(Rk, Sk, out, counts)
@@ -351,7 +363,7 @@ def main():
     log(f"signature join: {ms_step:.3f} ms/step; phases {phase_ms}")
 
     tab_cap = 64
-    while tab_cap * 0.5 < w.R.n:
+    while tab_cap * lf < w.R.n:
         tab_cap <<= 1
     slots_per_key = expected_slots(w.R.n, tab_cap, n_pairs / max(1, w.S.n))
     nbytes = {
@@ -387,6 +399,7 @@ def main():
     plain = None
     if not args.no_plain:
         counts_p = torch.zeros(2, dtype=torch.int64, device="cuda")
+        tune_plain = None if args.no_autotune else A.autotune(Rk, Sk, out, counts_p, flags=A.ASJ_PLAIN)
         for _ in range(max(1, args.warmup)):
             A.asj_join(Rk, Sk, out, counts_p, flags=A.ASJ_PLAIN)
         ms_plain, plain_phase, _ = run_steps(A, torch, Rk, Sk, out, counts_p, args.steps, flags=A.ASJ_PLAIN)
@@ -394,7 +407,7 @@ def main():
         plain = {"ms_per_step": round(ms_plain, 4), "value": round(w.S.n / (ms_plain * 1e-3), 1),
                  "unit": "probe tuples/s", "slots_compared": int(counts_p[1]),
                  "phases_ms": {k: round(v, 4) for k, v in plain_phase.items()},
-                 "signature_join_speedup": round(ms_plain / ms_step, 3)}
+                 "signature_join_speedup": round(ms_plain / ms_step, 3), "autotune": tune_plain}
         log(f"plain hash join: {ms_plain:.3f} ms/step")
 
     if args.calibrate_copy > 0:
@@ -412,14 +425,14 @@ def main():
         bw = W.batch(scale=args.batch_scale)
         log(f"generated batch J={bw.njoins} R={bw.R.n} S={bw.S.n} bytes={bw.R.nbytes + bw.S.nbytes} "
             f"in {time.perf_counter() - t:.1f}s")
-        batched = bench_batch(A, torch, bw, max(3, args.steps // 2), args.warmup)
+        batched = bench_batch(A, torch, bw, max(3, args.steps // 2), args.warmup, autotune=not args.no_autotune)
         batched["workload"] = (f"batch of 256 joins at {args.batch_scale:g} scale: |R_j| log-uniform 100-200k, "
                                f"|S_j| = U(1,8)|R_j|, XML-like keys log-uniform 16-2048 B, 25% copies")
         log(f"batch: {batched}")
     tiny_batch = None
     if args.tiny_instances > 0:
         tw = tiny_instances(W, args.tiny_instances)
-        tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup)
+        tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup, autotune=not args.no_autotune)
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
         log(f"tiny batch: {tiny_batch}")
 
@@ -460,7 +473,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "scale": args.scale, "seed": seed,
                    "R": w.R.n, "S": w.S.n, "key_bytes": w.R.nbytes + w.S.nbytes, "signature": "GF(2^16), n=2",
-                   "load_factor": 0.5, "pairs": n_pairs, "candidates": n_cand, "parallelism": "1 GPU"},
+                   "load_factor": lf, "keys_per_window": tune["keys_per_window"] if tune else 64,
+                   "probe_schedule": tune["schedule"] if tune else "fused", "pairs": n_pairs, "candidates": n_cand, "parallelism": "1 GPU"},
         "hbm_gbps_step": round(step_gbps, 1),
         "frac_peak_step": round(step_gbps / HBM_PEAK_GBPS, 4),
         "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
@@ -469,6 +483,7 @@ def main():
         "batched": batched,
         "tiny_batched": tiny_batch,
         "served": served,
+        "autotune": tune,
         "cpu_baseline": cpu,
         "check": {"pairs_match_expected": n_pairs == expected and check == n_pairs},
     }

@@ -91,11 +91,15 @@ typedef struct asj_sig_params {
     int32_t nsym;
 } asj_sig_params;
 
-/* Join options.  sig = {0, 0} means {16, 2}; load_factor <= 0 means 0.5
- * (table capacity = next power of two >= m / load_factor, at least 64);
- * keys_per_window = probe keys a wave takes at a time, 1..64 (<= 0: the
- * library's default); it trades lane use in the probe walk against how
- * soon a probe key is re-read for verification after it was signed. */
+/* Join options.  sig = {0, 0} means {16, 2}; load_factor = table fill
+ * bound (capacity = next power of two >= m / load_factor, at least 64);
+ * keys_per_window = probe keys a wave takes at a time, 1..64.  Options left
+ * to the library -- load_factor <= 0, keys_per_window <= 0, neither
+ * ASJ_PROBE_FUSED nor ASJ_PROBE_SPLIT -- take the value asj_autotune (or
+ * asj_autotune_batch for asj_join_batch) recorded on this device for the
+ * same size class (build rows rounded up to a power of two, same signature
+ * parameters and ASJ_PLAIN / ASJ_NO_VERIFY flags), else the defaults 0.5,
+ * 64 and the fused schedule. */
 typedef struct asj_opts {
     asj_sig_params sig;
     float load_factor;
@@ -204,6 +208,37 @@ typedef struct asj_batch {
 int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts);
 
 int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream);
+
+/* ---- autotuning ---- */
+
+/* Outcome of an autotuning run. */
+typedef struct asj_tune_result {
+    asj_opts best;    /* fastest options found (explicit values and schedule flag) */
+    float best_ms;    /* median time of one whole call with `best` */
+    float default_ms; /* median time with the defaults (0.5, 64, fused) */
+    int32_t trials;   /* configurations timed besides the defaults */
+} asj_tune_result;
+
+/* Autotuner for asj_join: times whole joins of r and s (one untimed and
+ * three timed calls per configuration, median, HIP events on `stream`) over
+ * the load factors {0.25, 0.35, 0.5, 0.7} that give distinct capacities,
+ * keys_per_window {16, 32, 64} and both probe schedules, with the signature
+ * parameters and ASJ_PLAIN / ASJ_NO_VERIFY flags of `opts` (NULL = defaults;
+ * its load factor, keys per window and schedule are ignored), and records the
+ * fastest for later calls that leave these options to the library (see
+ * asj_opts).  out, out_cap and out_count are the result buffers of the trial
+ * joins (as for asj_join); `res` (may be NULL) receives the outcome.
+ * Synchronizes the stream.  Errors: those of asj_join, ASJ_EINVAL. */
+int asj_autotune(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+                 int64_t *out_count, asj_tune_result *res, hipStream_t stream);
+
+/* The same for asj_join_batch over the batch `b` (all four load factors;
+ * b's workspace is not used: each trial allocates its own, stream-ordered).
+ * b's outputs receive the trial results. */
+int asj_autotune_batch(const asj_batch *b, const asj_opts *opts, asj_tune_result *res, hipStream_t stream);
+
+/* Forget every recorded tuning result. */
+void asj_autotune_clear(void);
 
 /* Frequency of the device constant clock used by done_clock, in kHz. */
 int64_t asj_clock_khz(void);

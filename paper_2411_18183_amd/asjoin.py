@@ -58,6 +58,11 @@ class asj_batch(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
 
 
+class asj_tune_result(ctypes.Structure):
+    _fields_ = [("best", asj_opts), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("trials", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -85,10 +90,17 @@ def lib():
         L.asj_batch_workspace_bytes.argtypes = [ctypes.c_int32, I64, I64, ctypes.POINTER(asj_opts)]
         L.asj_batch_workspace_bytes.restype = I64
         L.asj_join_batch.argtypes = [ctypes.POINTER(asj_batch), ctypes.POINTER(asj_opts), P]
+        L.asj_autotune.argtypes = [ctypes.POINTER(asj_keys), ctypes.POINTER(asj_keys), ctypes.POINTER(asj_opts), P,
+                                   I64, P, ctypes.POINTER(asj_tune_result), P]
+        L.asj_autotune_batch.argtypes = [ctypes.POINTER(asj_batch), ctypes.POINTER(asj_opts),
+                                         ctypes.POINTER(asj_tune_result), P]
+        L.asj_autotune_clear.argtypes = []
+        L.asj_autotune_clear.restype = None
         L.asj_clock_khz.argtypes = []
         L.asj_clock_khz.restype = I64
         for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_table_status", "asj_table_free",
-                     "asj_timing_enable", "asj_timing_read", "asj_util_copy", "asj_join_batch"):
+                     "asj_timing_enable", "asj_timing_read", "asj_util_copy", "asj_join_batch", "asj_autotune",
+                     "asj_autotune_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -181,7 +193,7 @@ def _opts(f, nsym, load_factor, flags, keys_per_window=0) -> asj_opts:
     return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags), int(keys_per_window))
 
 
-def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.5, flags: int = 0,
+def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.0, flags: int = 0,
               keys_per_window: int = 0, stream=None) -> Table:
     k = R.c()
     o = _opts(f, nsym, load_factor, flags, keys_per_window)
@@ -200,7 +212,7 @@ def asj_probe(t: Table, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, 
 
 
 def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, f: int = 16, nsym: int = 2,
-             load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0, stream=None):
+             load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, stream=None):
     """Launch a whole join.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
     kr, ks = R.c(), S.c()
     o = _opts(f, nsym, load_factor, flags, keys_per_window)
@@ -261,7 +273,7 @@ def _ptr(t):
 
 
 def asj_batch_workspace_bytes(njoins: int, n_build: int, n_probe: int, f: int = 16, nsym: int = 2,
-                              load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0) -> int:
+                              load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0) -> int:
     o = _opts(f, nsym, load_factor, flags, keys_per_window)
     v = lib().asj_batch_workspace_bytes(int(njoins), int(n_build), int(n_probe), ctypes.byref(o))
     if v < 0:
@@ -272,7 +284,7 @@ def asj_batch_workspace_bytes(njoins: int, n_build: int, n_probe: int, f: int = 
 def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: torch.Tensor, out: torch.Tensor,
                    out_seg: torch.Tensor, out_count: torch.Tensor, cand_count: Optional[torch.Tensor] = None,
                    done_clock: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None, f: int = 16,
-                   nsym: int = 2, load_factor: float = 0.5, flags: int = 0, keys_per_window: int = 0, stream=None):
+                   nsym: int = 2, load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, stream=None):
     """Launch a batch of joins (see asj_batch in the header).  All tensors on the device:
     r_seg/s_seg/out_seg int64 [J+1], out int32 [*, 2], out_count (and cand_count) int64 [J],
     done_clock int64 [J+1] (device clock ticks), workspace uint8 (optional)."""
@@ -285,6 +297,43 @@ def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: tor
                   int(workspace.numel()) if workspace is not None else 0)
     o = _opts(f, nsym, load_factor, flags, keys_per_window)
     _check(lib().asj_join_batch(ctypes.byref(b), ctypes.byref(o), _stream(stream)), "asj_join_batch")
+
+
+def _tune_dict(r: asj_tune_result) -> dict:
+    b = r.best
+    sched = "split" if b.flags & ASJ_PROBE_SPLIT else "fused"
+    return {"load_factor": round(float(b.load_factor), 4), "keys_per_window": int(b.keys_per_window),
+            "schedule": sched, "best_ms": round(float(r.best_ms), 4), "default_ms": round(float(r.default_ms), 4),
+            "trials": int(r.trials)}
+
+
+def autotune(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, out_count: torch.Tensor, f: int = 16, nsym: int = 2,
+             flags: int = 0, stream=None) -> dict:
+    """Run the library's autotuner on these relations (see asj_autotune); later calls that leave the load
+    factor, keys per window and schedule at 0 use its choice."""
+    rk, sk = R.c(), S.c()
+    o = _opts(f, nsym, 0.0, flags)
+    res = asj_tune_result()
+    _check(lib().asj_autotune(ctypes.byref(rk), ctypes.byref(sk), ctypes.byref(o), _ptr(out), out.shape[0],
+                              _ptr(out_count), ctypes.byref(res), _stream(stream)), "asj_autotune")
+    return _tune_dict(res)
+
+
+def autotune_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: torch.Tensor, out: torch.Tensor,
+                   out_seg: torch.Tensor, out_count: torch.Tensor, f: int = 16, nsym: int = 2, flags: int = 0,
+                   stream=None) -> dict:
+    J = r_seg.numel() - 1
+    b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count), None,
+                  None, None, 0)
+    o = _opts(f, nsym, 0.0, flags)
+    res = asj_tune_result()
+    _check(lib().asj_autotune_batch(ctypes.byref(b), ctypes.byref(o), ctypes.byref(res), _stream(stream)),
+           "asj_autotune_batch")
+    return _tune_dict(res)
+
+
+def autotune_clear():
+    lib().asj_autotune_clear()
 
 
 def clock_khz() -> int:

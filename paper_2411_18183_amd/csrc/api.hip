@@ -120,14 +120,25 @@ int resolve_sig(asj_sig_params p, asj_sig_params *out)
     return ASJ_EUNSUPPORTED;
 }
 
-// Probe schedule from the flags: 1 = split (sign kernel, then a probe
-// kernel with the stored signatures), 0 = fused; -1 = contradictory flags.
-int probe_split(uint32_t flags)
+// Table load factor, probe keys per window and probe schedule (1 = split:
+// sign kernel, then a probe kernel with the stored signatures; 0 = fused)
+// for options that may leave them to the library: a value the caller set
+// wins, then the autotuner's record for this size class, then the defaults
+// (0.5, 64, fused -- fused was faster on every measured workload).
+// ASJ_EINVAL for contradictory schedule flags or a load factor >= 1.
+int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *kpw, int *split)
 {
-    const bool fused = (flags & ASJ_PROBE_FUSED) != 0, split = (flags & ASJ_PROBE_SPLIT) != 0;
-    if (fused && split) return -1;
-    if (split) return 1;
-    return 0; // default schedule: fused (faster on every measured workload)
+    const bool fused = (o.flags & ASJ_PROBE_FUSED) != 0, sp = (o.flags & ASJ_PROBE_SPLIT) != 0;
+    if (fused && sp) return ASJ_EINVAL;
+    asj_tuned t = {};
+    const bool tuned = asj_tuned_lookup(batch, n_build, o, &t);
+    *lf = o.load_factor > 0.0f ? o.load_factor : (tuned ? t.load_factor : 0.5f);
+    if (!(*lf > 0.0f && *lf < 1.0f)) return ASJ_EINVAL;
+    *kpw = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE)
+               ? o.keys_per_window
+               : (tuned ? t.keys_per_window : ASJ_DEFAULT_KEYS_PER_WINDOW);
+    *split = fused ? 0 : sp ? 1 : (tuned ? t.split : 0);
+    return ASJ_OK;
 }
 
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
@@ -154,15 +165,14 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     const int plain = (o.flags & ASJ_PLAIN) != 0;
     const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (plain && !verify) return ASJ_EINVAL; // the plain table has no signature to trust
-    const int split = probe_split(o.flags);
-    if (split < 0) return ASJ_EINVAL;
     asj_sig_params sig = {16, 2};
     if (!plain) {
         int rc = resolve_sig(o.sig, &sig);
         if (rc != ASJ_OK) return rc;
     }
-    float lf = o.load_factor > 0.0f ? o.load_factor : 0.5f;
-    if (!(lf > 0.0f && lf < 1.0f)) return ASJ_EINVAL;
+    float lf;
+    int kpw, split;
+    if (resolve_auto(0, r->n, o, &lf, &kpw, &split) != ASJ_OK) return ASJ_EINVAL;
     int dev = 0;
     int rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
@@ -177,8 +187,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->plain = plain;
     t->verify = verify;
     t->sig = sig;
-    t->keys_per_window = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE) ? o.keys_per_window
-                                                                                  : ASJ_DEFAULT_KEYS_PER_WINDOW;
+    t->keys_per_window = kpw;
     t->split = split;
     t->stream = st;
     t->device = dev;
@@ -321,28 +330,20 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     return true;
 }
 
-int batch_opts(const asj_opts *opts, int *plain, int *verify, asj_sig_params *sig, float *lf, int *kpw = nullptr,
-               int *split = nullptr)
+int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
+               int *kpw, int *split)
 {
     asj_opts o = {};
     if (opts) o = *opts;
     *plain = (o.flags & ASJ_PLAIN) != 0;
     *verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (*plain && !*verify) return ASJ_EINVAL;
-    const int sp = probe_split(o.flags);
-    if (sp < 0) return ASJ_EINVAL;
-    if (split) *split = sp;
     *sig = asj_sig_params{16, 2};
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);
         if (rc != ASJ_OK) return rc;
     }
-    *lf = o.load_factor > 0.0f ? o.load_factor : 0.5f;
-    if (!(*lf > 0.0f && *lf < 1.0f)) return ASJ_EINVAL;
-    if (kpw)
-        *kpw = (o.keys_per_window >= 1 && o.keys_per_window <= ASJ_WAVE) ? o.keys_per_window
-                                                                        : ASJ_DEFAULT_KEYS_PER_WINDOW;
-    return ASJ_OK;
+    return resolve_auto(1, n_build, o, lf, kpw, split);
 }
 
 } // namespace
@@ -473,10 +474,10 @@ int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
 
 int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts)
 {
-    int plain, verify, kpw;
+    int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    if (batch_opts(opts, &plain, &verify, &sig, &lf, &kpw) != ASJ_OK) return -1;
+    if (batch_opts(opts, n_build, &plain, &verify, &sig, &lf, &kpw, &split) != ASJ_OK) return -1;
     BatchLayout L;
     if (!batch_layout(njoins, n_build, n_probe, kpw, lf, &L)) return -1;
     return (int64_t)L.bytes;
@@ -491,7 +492,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int rc = batch_opts(opts, &plain, &verify, &sig, &lf, &kpw, &split);
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;

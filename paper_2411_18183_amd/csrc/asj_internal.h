@@ -181,6 +181,17 @@ struct asj_table {
     int device;
 };
 
+// Options recorded by the autotuner for a size class (build rows rounded
+// up to a power of two, signature parameters, plain/verify flags, single
+// join or batch) on the current device.
+struct asj_tuned {
+    float load_factor;
+    int keys_per_window;
+    int split;
+};
+bool asj_tuned_lookup(int batch, int64_t n_build, const asj_opts &o, asj_tuned *t);
+void asj_tuned_store(int batch, int64_t n_build, const asj_opts &o, const asj_tuned &t);
+
 // GF constant tables of the current device (initialising the library on
 // first use); nullptr on failure.
 const uint16_t *asj_device_tables(int *dev);

@@ -1,0 +1,202 @@
+// Autotuner: times whole joins over a grid of table load factors, probe
+// keys per window and both probe schedules on the caller's relations, keeps
+// the fastest, and records it per build-size class so that later calls that
+// leave these options at zero use it.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "asj_internal.h"
+
+namespace {
+
+struct Key {
+    int dev, batch, bucket, f, nsym, plain, verify;
+    bool operator<(const Key &o) const
+    {
+        return std::tie(dev, batch, bucket, f, nsym, plain, verify) <
+               std::tie(o.dev, o.batch, o.bucket, o.f, o.nsym, o.plain, o.verify);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<Key, asj_tuned> g_tuned;
+
+int log2_bucket(int64_t n)
+{
+    int b = 0;
+    while (b < 62 && (1LL << b) < n) b++;
+    return b;
+}
+
+Key make_key(int batch, int64_t n_build, const asj_opts &o)
+{
+    Key k = {};
+    (void)hipGetDevice(&k.dev);
+    k.batch = batch;
+    k.bucket = log2_bucket(n_build);
+    k.plain = (o.flags & ASJ_PLAIN) != 0;
+    k.verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    k.f = k.plain ? 0 : (o.sig.f ? o.sig.f : 16);
+    k.nsym = k.plain ? 0 : (o.sig.nsym ? o.sig.nsym : 2);
+    return k;
+}
+
+constexpr float kLoadFactors[] = {0.25f, 0.35f, 0.5f, 0.7f};
+constexpr int kKeysPerWindow[] = {16, 32, 64};
+constexpr int kReps = 3;
+
+int64_t capacity_for(int64_t n, float lf)
+{
+    int64_t cap = 64;
+    while ((double)cap * lf < (double)n) cap <<= 1;
+    return cap;
+}
+
+// Median of kReps timed runs after one untimed run; the result of run() is
+// checked on every call.
+template <class Run>
+int time_runs(Run run, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    int rc = run();
+    if (rc != ASJ_OK) return rc;
+    float t[kReps];
+    for (int i = 0; i < kReps; i++) {
+        if (hipEventRecord(e0, st) != hipSuccess) return ASJ_EHIP;
+        rc = run();
+        if (rc != ASJ_OK) return rc;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ASJ_EHIP;
+        if (hipEventElapsedTime(&t[i], e0, e1) != hipSuccess) return ASJ_EHIP;
+    }
+    std::sort(t, t + kReps);
+    *ms = t[kReps / 2];
+    return ASJ_OK;
+}
+
+// The grid: every load factor that gives a distinct table capacity for
+// n_build rows (all four for a batch, whose segments differ), every keys per
+// window, both schedules.
+std::vector<asj_opts> grid(const asj_opts &base, int64_t n_build, bool batch)
+{
+    std::vector<asj_opts> g;
+    std::vector<int64_t> caps;
+    const uint32_t flags = base.flags & ~(ASJ_PROBE_FUSED | ASJ_PROBE_SPLIT);
+    for (float lf : kLoadFactors) {
+        if (!batch) {
+            const int64_t c = capacity_for(n_build, lf);
+            if (std::find(caps.begin(), caps.end(), c) != caps.end()) continue;
+            caps.push_back(c);
+        }
+        for (int kpw : kKeysPerWindow)
+            for (uint32_t sched : {ASJ_PROBE_FUSED, ASJ_PROBE_SPLIT}) {
+                asj_opts o = base;
+                o.load_factor = lf;
+                o.keys_per_window = kpw;
+                o.flags = flags | sched;
+                g.push_back(o);
+            }
+    }
+    return g;
+}
+
+template <class RunWith>
+int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, asj_tune_result *res, hipStream_t st)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return ASJ_EHIP;
+    }
+    int rc = ASJ_OK;
+    asj_opts defaults = base;
+    defaults.load_factor = 0.5f;
+    defaults.keys_per_window = ASJ_DEFAULT_KEYS_PER_WINDOW;
+    defaults.flags = (base.flags & ~(ASJ_PROBE_FUSED | ASJ_PROBE_SPLIT)) | ASJ_PROBE_FUSED;
+    float def_ms = 0.0f, best_ms = 0.0f;
+    asj_opts best = defaults;
+    int trials = 0;
+    rc = time_runs([&] { return run_with(defaults); }, st, e0, e1, &def_ms);
+    best_ms = def_ms;
+    if (rc == ASJ_OK) {
+        for (const asj_opts &o : grid(base, n_build, batch)) {
+            float ms = 0.0f;
+            rc = time_runs([&] { return run_with(o); }, st, e0, e1, &ms);
+            if (rc != ASJ_OK) break;
+            trials++;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = o;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != ASJ_OK) return rc;
+    asj_tuned t = {best.load_factor, best.keys_per_window, (best.flags & ASJ_PROBE_SPLIT) ? 1 : 0};
+    asj_tuned_store(batch ? 1 : 0, n_build, base, t);
+    if (res) {
+        res->best = best;
+        res->best_ms = best_ms;
+        res->default_ms = def_ms;
+        res->trials = trials;
+    }
+    return ASJ_OK;
+}
+
+bool tunable(const asj_opts &o)
+{
+    return !((o.flags & ASJ_PROBE_FUSED) && (o.flags & ASJ_PROBE_SPLIT)) && o.load_factor >= 0.0f &&
+           o.load_factor < 1.0f && o.keys_per_window <= ASJ_WAVE;
+}
+
+} // namespace
+
+bool asj_tuned_lookup(int batch, int64_t n_build, const asj_opts &o, asj_tuned *t)
+{
+    const Key k = make_key(batch, n_build, o);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(k);
+    if (it == g_tuned.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+void asj_tuned_store(int batch, int64_t n_build, const asj_opts &o, const asj_tuned &t)
+{
+    const Key k = make_key(batch, n_build, o);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[k] = t;
+}
+
+extern "C" {
+
+int asj_autotune(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+                 int64_t *out_count, asj_tune_result *res, hipStream_t st)
+{
+    asj_opts base = {};
+    if (opts) base = *opts;
+    if (!r || !s || !out_count || out_cap < 0 || (out_cap > 0 && !out) || !tunable(base)) return ASJ_EINVAL;
+    return tune(base, r->n, false,
+                [&](const asj_opts &o) { return asj_join(r, s, &o, out, out_cap, out_count, nullptr, st); }, res, st);
+}
+
+int asj_autotune_batch(const asj_batch *b, const asj_opts *opts, asj_tune_result *res, hipStream_t st)
+{
+    asj_opts base = {};
+    if (opts) base = *opts;
+    if (!b || !tunable(base)) return ASJ_EINVAL;
+    asj_batch trial = *b;
+    trial.workspace = nullptr; // every configuration sizes its own (stream-ordered, pooled) workspace
+    trial.workspace_bytes = 0;
+    return tune(base, b->r.n, true, [&](const asj_opts &o) { return asj_join_batch(&trial, &o, st); }, res, st);
+}
+
+void asj_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+} // extern "C"

@@ -56,3 +56,9 @@ def test_invalid_arguments_are_rejected_before_any_device_work(lib):
     assert lib.asj_table_free(None) == 0
     lib.asj_table_capacity.restype = ctypes.c_int64
     assert lib.asj_table_capacity(None) == -1
+    lib.asj_autotune.restype = ctypes.c_int
+    assert lib.asj_autotune(None, None, None, None, ctypes.c_int64(0), None, None, None) == -1
+    lib.asj_autotune_batch.restype = ctypes.c_int
+    assert lib.asj_autotune_batch(None, None, None, None) == -1
+    lib.asj_autotune_clear.restype = None
+    lib.asj_autotune_clear()
