@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="size of the resident build side of the serving run (1.0 = 10M keys; 0 = skip)")
     ap.add_argument("--serve-arrivals", type=int, default=48)
+    ap.add_argument("--length-sweep", action="store_true",
+                    help="also time signature vs plain joins on keys of one length, 4 B .. 4 KB")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -167,6 +169,26 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     ck = clock.cpu().numpy()
     lat = (ck[:-1] - ck[-1]) / khz  # ms after the batch started on the device
     assert (cnt.cpu().numpy() == counts).all(), "batched counts changed between runs"
+    # the plain byte-compare hash join through the same batched path
+    flags_p = A.ASJ_PLAIN
+    tune_plain = None
+    if autotune:
+        tune_plain = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"),
+                                      flags=flags_p)
+    cnt_p = torch.zeros(J, dtype=torch.int64, device="cuda")
+    ws_p = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n, bw.S.n, flags=flags_p), dtype=torch.uint8, device="cuda")
+    run_p = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt_p, None, None, workspace=ws_p, flags=flags_p)
+    for _ in range(max(1, warmup)):
+        run_p()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run_p()
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3 / steps
+    assert (cnt_p.cpu().numpy() == counts).all(), "plain batched join disagrees on |T_j|"
+    run()  # the signature join's output again in `out`
+    torch.cuda.synchronize()
     ms_graph = None
     if graph:
         st = torch.cuda.Stream()
@@ -223,7 +245,42 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
                                       "p99": round(float(np.percentile(lat_unb, 99)), 4)},
         "unbatched_counts_match": bool(ok),
         "autotune": tune,
+        "plain_ms_batched": round(ms_plain, 4), "plain_autotune": tune_plain,
+        "signature_join_speedup": round(ms_plain / ms_direct, 3),
     }
+
+
+def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096),
+                       probe_bytes: int = 1 << 29):
+    """Signature join vs plain byte-compare hash join on keys of one length
+    (R = |S| / 4, 20% of S copies R rows, bytes uniform over all 256 values;
+    |S| = min(4M, probe_bytes / length)), both with the same fixed options
+    (load factor 0.5, 64 keys per window, fused schedule)."""
+    rows = []
+    for L in lengths:
+        n = int(min(4_000_000, probe_bytes // L))
+        w = W.fixed_length(seed=20, m=n // 4, n=n, key_len=L)
+        Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+        out = torch.empty((n + n // 4, 2), dtype=torch.int32, device="cuda")
+        res = {"key_len": L, "R": w.R.n, "S": n}
+        for name, flags in (("signature", 0), ("plain", A.ASJ_PLAIN)):
+            cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+            fl = flags | A.ASJ_PROBE_FUSED
+            run = lambda: A.asj_join(Rk, Sk, out, cnt, load_factor=0.5, keys_per_window=64, flags=fl)
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                run()
+            torch.cuda.synchronize()
+            res[f"ms_{name}"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+            res[f"pairs_{name}"] = int(cnt[0])
+        assert res["pairs_signature"] == res["pairs_plain"], res
+        res["signature_join_speedup"] = round(res["ms_plain"] / res["ms_signature"], 3)
+        log(f"length sweep: {res}")
+        rows.append(res)
+        del Rk, Sk, out, w
+    return rows
 
 
 def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, seed: int = 5):
@@ -436,6 +493,10 @@ def main():
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
         log(f"tiny batch: {tiny_batch}")
 
+    sweep = None
+    if args.length_sweep:
+        sweep = bench_length_sweep(A, torch, W, max(3, args.steps // 4))
+
     served = None
     if args.serve_scale > 0:
         served = bench_serving(A, torch, W, args.serve_scale, 16, args.serve_arrivals)
@@ -484,6 +545,7 @@ def main():
         "tiny_batched": tiny_batch,
         "served": served,
         "autotune": tune,
+        "length_sweep": sweep,
         "cpu_baseline": cpu,
         "check": {"pairs_match_expected": n_pairs == expected and check == n_pairs},
     }

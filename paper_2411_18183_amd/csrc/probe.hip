@@ -27,7 +27,8 @@
 //      per flush; a single output counter hit once per round and wave had
 //      cost 11% of the kernel.
 // The baseline simple hash join runs the same kernel with the plain key hash
-// and treats every occupied slot as a candidate (no signature stored).
+// and treats every occupied slot as a candidate (no signature stored); its
+// byte comparison stops after the first 64 bytes when they differ.
 // In batch mode windows never span two joins: a window reads its join from
 // the window map, probes that join's table segment, appends to that join's
 // output segment, and the wave that finishes a join's last probe row stamps
@@ -220,9 +221,27 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_prob
                     rs = (int64_t)o.x;
                     lr = (int)((int64_t)o.y - rs);
                 }
-                const bool eq = has && lr == ls;
-                // the chunks of every equal-length pair, one per lane
-                const int nch = eq ? (ls + ASJ_CHUNK - 1) / ASJ_CHUNK : 0;
+                bool eq = has && lr == ls;
+                if (PLAIN && eq) {
+                    // The plain table offers every occupied slot as a candidate, so
+                    // most equal-length pairs differ: each lane compares its pair's
+                    // first 64 bytes (or whole key) alone, and only pairs that agree
+                    // there go on to the chunk passes below.
+                    uint32_t kr[16], ks[16], diff = 0;
+                    if (ls >= ASJ_CHUNK) {
+                        asj_load_full(a.rdata, rs, kr);
+                        asj_load_full(a.sdata, ss, ks);
+                    } else {
+                        asj_load_tail(a.rdata, rs, ls, kr);
+                        asj_load_tail(a.sdata, ss, ls, ks);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                    eq = diff == 0;
+                }
+                // the (remaining) chunks of every equal-length pair, one per lane
+                constexpr int kFirst = PLAIN ? 1 : 0; // chunks already compared
+                const int nch = eq ? max(0, (ls + ASJ_CHUNK - 1) / ASJ_CHUNK - kFirst) : 0;
                 const int incl = asj_wave_incl_scan(nch);
                 const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
                 wst[lane] = ss;
@@ -235,7 +254,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_prob
                     const int x = base + lane;
                     if (x < total) {
                         const int i = asj_find_owner(wex, x);
-                        const int c = x - wex[i];
+                        const int c = x - wex[i] + kFirst;
                         const int L = wln[i];
                         uint32_t diff = 0;
                         if (L >= ASJ_CHUNK) {

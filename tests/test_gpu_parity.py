@@ -241,3 +241,25 @@ def test_contradictory_schedule_flags_rejected(A, wl):
     w = wl.random_small(1, m=10, n=10)
     with pytest.raises(A.AsjError):
         gpu_join(A, w.R, w.S, flags=A.ASJ_PROBE_FUSED | A.ASJ_PROBE_SPLIT)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_plain_baseline_long_shared_prefixes(A, oracle, wl, sched):
+    """Keys that agree on their first 64 bytes (or more) and differ later, at
+    lengths around the chunk boundaries: the plain join's first-chunk compare
+    passes them on and the remaining chunks must decide."""
+    rng = np.random.default_rng(31)
+    prefix = bytes(rng.integers(0, 256, size=300, dtype=np.uint8))
+    keys_r, keys_s = [], []
+    for i, L in enumerate([1, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 300] * 6):
+        base = bytearray(prefix[:L])
+        base[-1] = i % 256
+        keys_r.append(bytes(base))
+        near = bytearray(base)
+        near[-1] ^= 0x5A  # differs only in its last byte
+        keys_s += [bytes(base), bytes(near)]
+    R, S = wl.from_keys(keys_r), wl.from_keys(keys_s)
+    want = oracle.join_nested(R, S)
+    for flags in (A.ASJ_PLAIN, 0):
+        got, total, _ = gpu_join(A, R, S, sched=sched, flags=flags)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)

@@ -383,3 +383,11 @@ def test_batch_workload_joins_scaled(oracle, wl):
         pairs, _ = oracle.join_signature(j.R, j.S)
         assert np.array_equal(pairs, oracle.join_hash(j.R, j.S))
         assert len(pairs) >= int(0.1 * j.S.n) or j.S.n < 40
+
+
+def test_fixed_length_workload_structure(oracle, wl):
+    w = wl.fixed_length(seed=3, m=500, n=2000, key_len=9)
+    assert (w.R.lengths() == 9).all() and (w.S.lengths() == 9).all()
+    assert w.meta["copies"] == 400
+    pairs = oracle.join_hash(w.R, w.S)
+    assert len(pairs) >= 400  # every copy matches its source row (more only through equal random keys)

@@ -187,6 +187,28 @@ def tiny(seed: int = 1, scale: float = 1.0, key_len: int = 256) -> Workload:
     return Workload("tiny", R, S, {"copies": ncopy, "expected_matches": ncopy, "seed": seed, "scale": scale})
 
 
+def fixed_length(seed: int, m: int, n: int, key_len: int, copy_frac: float = 0.2,
+                 alphabet: np.ndarray | None = None) -> Workload:
+    """Keys of one length (the key-length sweep): R = m random keys, S = n
+    keys of which round(copy_frac * n) copy uniformly drawn R rows.  Bytes
+    are uniform over `alphabet` (default: all 256 values, so short keys stay
+    nearly distinct)."""
+    alphabet = np.arange(256, dtype=np.uint8) if alphabet is None else alphabet
+    rng = np.random.default_rng([seed, 8, key_len])
+    rd, ro = _alloc(np.full(m, key_len))
+    _fill(rd, ro, None, seed, _STREAM["R"], alphabet)
+    R = Relation(rd, ro, _row_ids(m))
+    ncopy = int(round(copy_frac * n))
+    copy_rows = np.sort(rng.permutation(n)[:ncopy])
+    copy_src = rng.integers(0, m, size=ncopy)
+    sd, so = _alloc(np.full(n, key_len))
+    fresh = np.setdiff1d(np.arange(n), copy_rows)
+    _fill(sd, so, fresh, seed, _STREAM["S"], alphabet)
+    _copy(sd, so, copy_rows, R, copy_src)
+    S = Relation(sd, so, _row_ids(n))
+    return Workload(f"fixed{key_len}", R, S, {"copies": ncopy, "seed": seed, "key_len": key_len})
+
+
 # ---------------------------------------------------------------------------
 # large: R = 1M, S = 4M, log-uniform [64, 4096], 48-byte shared prefix, Zipf(1)
 # ---------------------------------------------------------------------------
