@@ -104,7 +104,11 @@ __global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap
 }
 
 // Lane l of build window w inserts row r_seg[j] + 64 (w - wbase_r) + l of
-// join j = win_r[w] into the join's segment (linear probing, 64-bit CAS).
+// join j = win_r[w] into the join's segment, in the two passes of the
+// single-join build (table.hip): STORE = 1 stores every row into its home
+// slot, STORE = 0 moves the rows that lost their home slot to the first
+// empty slot after it with CAS.
+template <int STORE>
 __global__ void insert_batch_kernel(const uint32_t *__restrict__ sig, int64_t m, const int64_t *__restrict__ r_seg,
                                     const asj_join_desc *__restrict__ desc, const int32_t *__restrict__ win_r,
                                     const uint64_t *__restrict__ tot, int64_t win_cap, uint64_t *__restrict__ slots,
@@ -122,16 +126,21 @@ __global__ void insert_batch_kernel(const uint32_t *__restrict__ sig, int64_t m,
         const uint32_t sg = sig[g];
         const uint64_t val = ((uint64_t)sg << 32) | (uint32_t)g;
         uint64_t h = asj_mix32(sg) & d.mask;
+        if (STORE) {
+            slots[d.tbase + h] = val;
+            continue;
+        }
+        if (slots[d.tbase + h] == val) continue;
         uint64_t tries = 0;
         for (;;) {
-            const uint64_t old = atomicCAS((unsigned long long *)&slots[d.tbase + h],
-                                           (unsigned long long)ASJ_EMPTY_SLOT, (unsigned long long)val);
-            if (old == ASJ_EMPTY_SLOT) break;
             h = (h + 1) & d.mask;
             if (++tries > d.mask) {
                 atomicExch(status, (int32_t)ASJ_ETABLEFULL);
                 break;
             }
+            const uint64_t old = atomicCAS((unsigned long long *)&slots[d.tbase + h],
+                                           (unsigned long long)ASJ_EMPTY_SLOT, (unsigned long long)val);
+            if (old == ASJ_EMPTY_SLOT) break;
         }
     }
 }
@@ -172,7 +181,8 @@ hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t
                                    int32_t *status, hipStream_t st)
 {
     if (m <= 0 || win_r_cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(insert_batch_kernel, dim3(grid_for(win_r_cap * ASJ_WAVE, 256, 16384)), dim3(256), 0, st, sig,
-                       m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
+    const dim3 g(grid_for(win_r_cap * ASJ_WAVE, 256, 16384)), b(256);
+    hipLaunchKernelGGL(insert_batch_kernel<1>, g, b, 0, st, sig, m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
+    hipLaunchKernelGGL(insert_batch_kernel<0>, g, b, 0, st, sig, m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
     return hipGetLastError();
 }

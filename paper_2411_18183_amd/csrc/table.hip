@@ -2,9 +2,18 @@
 // placed in an open-addressing table of 64-bit slots
 //     slot = signature << 32 | row        (empty slot = all ones),
 // at mix32(signature) modulo the power-of-two capacity, moving to the next
-// slot while the CAS finds it taken (linear probing).  Rows with equal
-// signatures are all kept (a multimap): they share a home slot, so every
-// one of them lies on the run a probe walks until the first empty slot.
+// slot while it is taken (linear probing).  Rows with equal signatures are
+// all kept (a multimap): they share a home slot, so every one of them lies
+// on the run a probe walks until the first empty slot.
+//
+// Two passes instead of one CAS per row (64-bit CAS is about three times
+// slower than a store here): every row first stores itself into its home
+// slot (one of the rows sharing a home survives, whole, as 64-bit stores do
+// not tear); after that, a row that does not find itself there claims the
+// first empty slot after its home with CAS.  Every slot from a row's home to
+// its final slot is then occupied -- the home by the survivor, the rest
+// because the row's CAS found them taken and slots never empty again -- so
+// lookups find every row on the run from its home.
 //
 // The baseline simple hash join (Section 2) uses the same layout with the
 // plain key hash choosing the home slot and no signature stored (the high
@@ -31,7 +40,10 @@ __global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
         p[i] = v;
 }
 
-template <int PLAIN>
+// Pass 1 (STORE = 1): row r stores itself into its home slot.  Pass 2
+// (STORE = 0): a row that lost its home slot walks on from the next slot,
+// taking the first empty one with CAS.
+template <int PLAIN, int STORE>
 __global__ void insert_kernel(const uint32_t *__restrict__ sig, int64_t m, uint64_t *__restrict__ slots,
                               uint64_t mask, int32_t *__restrict__ status)
 {
@@ -39,16 +51,21 @@ __global__ void insert_kernel(const uint32_t *__restrict__ sig, int64_t m, uint6
         const uint32_t sg = sig[r];
         const uint64_t val = PLAIN ? (uint64_t)(uint32_t)r : (((uint64_t)sg << 32) | (uint32_t)r);
         uint64_t h = asj_mix32(sg) & mask;
+        if (STORE) {
+            slots[h] = val;
+            continue;
+        }
+        if (slots[h] == val) continue;
         uint64_t tries = 0;
         for (;;) {
-            const uint64_t old = atomicCAS((unsigned long long *)&slots[h], (unsigned long long)ASJ_EMPTY_SLOT,
-                                           (unsigned long long)val);
-            if (old == ASJ_EMPTY_SLOT) break;
             h = (h + 1) & mask;
             if (++tries > mask) { // every slot taken
                 atomicExch(status, (int32_t)ASJ_ETABLEFULL);
                 break;
             }
+            const uint64_t old = atomicCAS((unsigned long long *)&slots[h], (unsigned long long)ASJ_EMPTY_SLOT,
+                                           (unsigned long long)val);
+            if (old == ASJ_EMPTY_SLOT) break;
         }
     }
 }
@@ -88,11 +105,13 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
                              int32_t *status, hipStream_t st)
 {
     if (m <= 0) return hipSuccess;
-    if (plain)
-        hipLaunchKernelGGL(insert_kernel<1>, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, sig, m, slots, mask,
-                           status);
-    else
-        hipLaunchKernelGGL(insert_kernel<0>, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, sig, m, slots, mask,
-                           status);
+    const dim3 g(grid_for(m, 256, 16384)), b(256);
+    if (plain) {
+        hipLaunchKernelGGL((insert_kernel<1, 1>), g, b, 0, st, sig, m, slots, mask, status);
+        hipLaunchKernelGGL((insert_kernel<1, 0>), g, b, 0, st, sig, m, slots, mask, status);
+    } else {
+        hipLaunchKernelGGL((insert_kernel<0, 1>), g, b, 0, st, sig, m, slots, mask, status);
+        hipLaunchKernelGGL((insert_kernel<0, 0>), g, b, 0, st, sig, m, slots, mask, status);
+    }
     return hipGetLastError();
 }
