@@ -58,6 +58,11 @@ extern "C" {
                               path is compared by length and bytes (no stored fingerprint) */
 #define ASJ_PROBE_FUSED 0x4u /* probe schedule: each probe key is signed inside the probe kernel,
                                 right before its table walk and verification */
+#define ASJ_SORTED 0x10u      /* asj_join / asj_probe: the stored pairs (the first min(|T|, out_cap))
+                                are returned sorted by (r_id, s_id) as signed integers, by a device
+                                radix sort that reads |T| on the device (no host round trip; device
+                                scratch of 16 bytes per out_cap entry, stream-ordered).  Not
+                                supported by asj_join_batch (ASJ_EUNSUPPORTED). */
 #define ASJ_PROBE_SPLIT 0x8u /* probe schedule: the probe keys are signed by the signature kernel
                                 into a device scratch array first (4 bytes per key), then a probe
                                 kernel without signing walks and verifies.  Neither flag means

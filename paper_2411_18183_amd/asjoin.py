@@ -29,6 +29,7 @@ ASJ_NO_VERIFY = 0x1
 ASJ_PLAIN = 0x2
 ASJ_PROBE_FUSED = 0x4
 ASJ_PROBE_SPLIT = 0x8
+ASJ_SORTED = 0x10
 
 
 class AsjError(RuntimeError):

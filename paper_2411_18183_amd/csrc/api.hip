@@ -189,6 +189,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->sig = sig;
     t->keys_per_window = kpw;
     t->split = split;
+    t->sorted = (o.flags & ASJ_SORTED) != 0;
     t->stream = st;
     t->device = dev;
     uint32_t *sig_r = nullptr;
@@ -230,8 +231,26 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     return ASJ_OK;
 }
 
+int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
+                   int64_t *cand_count, hipStream_t st);
+
 int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
                int64_t *cand_count, hipStream_t st)
+{
+    int rc = probe_unsorted(t, s, out, out_cap, out_count, cand_count, st);
+    if (rc != ASJ_OK || !t->sorted || out_cap == 0) return rc;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, asj_sort_scratch_bytes(out_cap), st);
+    if (e != hipSuccess) return hip_fail(e);
+    tim_begin("sort", st);
+    e = asj_launch_sort_pairs(out, out_count, out_cap, scratch, st);
+    tim_end(st);
+    (void)hipFreeAsync(scratch, st);
+    return e == hipSuccess ? ASJ_OK : hip_fail(e);
+}
+
+int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
+                   int64_t *cand_count, hipStream_t st)
 {
     if (!t || !keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
     int dev = 0;
@@ -338,6 +357,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     *plain = (o.flags & ASJ_PLAIN) != 0;
     *verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (*plain && !*verify) return ASJ_EINVAL;
+    if (o.flags & ASJ_SORTED) return ASJ_EUNSUPPORTED;
     *sig = asj_sig_params{16, 2};
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);

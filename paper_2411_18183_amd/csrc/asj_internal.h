@@ -177,6 +177,7 @@ struct asj_table {
     asj_sig_params sig;  // signature parameters of the build
     int keys_per_window; // probe keys per wave window used by probes of this table
     int split;           // probes sign the probe keys in a separate kernel first
+    int sorted;          // probes sort their output pairs by (r_id, s_id)
     hipStream_t stream;  // build stream (orders free)
     int device;
 };
@@ -266,6 +267,10 @@ struct asj_probe_args {
 hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st);
 hipError_t asj_launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
+// Sorts pairs[0 .. min(*count, cap)) by (r_id, s_id); scratch holds
+// asj_sort_scratch_bytes(cap) device bytes.
+size_t asj_sort_scratch_bytes(int64_t cap);
+hipError_t asj_launch_sort_pairs(asj_pair *pairs, const int64_t *count, int64_t cap, void *scratch, hipStream_t st);
 hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int grid, hipStream_t st);
 
 // Batch: per-join segment plan (capacities, prefix offsets, counters, start

@@ -263,3 +263,56 @@ def test_plain_baseline_long_shared_prefixes(A, oracle, wl, sched):
     for flags in (A.ASJ_PLAIN, 0):
         got, total, _ = gpu_join(A, R, S, sched=sched, flags=flags)
         assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)
+
+
+def is_sorted_pairs(p):
+    if len(p) < 2:
+        return True
+    a = p[:, 0].astype(np.int64) * (1 << 33) + p[:, 1].astype(np.int64)
+    return bool((np.diff(a) >= 0).all())
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("seed", range(4))
+def test_sorted_output_equals_sorted_oracle(A, oracle, wl, sched, seed):
+    """ASJ_SORTED: the pairs come back in (r_id, s_id) order -- compared as
+    arrays, with no sorting on the host -- including negative ids, heavy
+    duplicates and the two-call pattern."""
+    w = wl.random_small(seed, m=300 + 50 * seed, n=900, max_len=[3, 9, 70, 200][seed], alphabet=b"ab\x00")
+    rng = np.random.default_rng(seed)
+    w.R.ids = (rng.permutation(w.R.n) - w.R.n // 2).astype(np.int32)  # negative and positive ids
+    w.S.ids = (rng.permutation(w.S.n) * 7 - 3000).astype(np.int32)
+    want = oracle.join_nested(w.R, w.S)
+    got, total, _ = gpu_join(A, w.R, w.S, sched=sched, flags=A.ASJ_SORTED, cap=16)
+    assert total == len(want)
+    assert np.array_equal(got, want)
+
+
+def test_sorted_output_larger_and_truncated(A, oracle, wl):
+    import torch
+    w = wl.large(scale=0.02)
+    Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+    want = oracle.join_hash(w.R, w.S)
+    got, total, _ = A.join(Rk, Sk, flags=A.ASJ_SORTED)
+    assert total == len(want) and np.array_equal(got.cpu().numpy(), want)
+    # out_cap below |T|: the stored pairs are sorted and belong to T
+    cap = len(want) // 3
+    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    A.asj_join(Rk, Sk, out, cnt, flags=A.ASJ_SORTED)
+    assert int(cnt[0]) == len(want)
+    part = out.cpu().numpy()
+    assert is_sorted_pairs(part)
+    key = lambda p: set(map(tuple, p.tolist()))
+    assert key(part) <= key(want) and len(key(part)) == cap
+    # no result at all
+    empty_s = wl.from_keys([b"\x01nothing"] * 10)
+    got, total, _ = A.join(Rk, A.DeviceKeys.from_host(empty_s), flags=A.ASJ_SORTED)
+    assert total == 0
+
+
+def test_sorted_not_supported_for_batches(A, wl):
+    w = wl.random_small(1, m=10, n=10)
+    R, S = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+    with pytest.raises(A.AsjError):
+        A.join_batch(R, S, [0, w.R.n], [0, w.S.n], flags=A.ASJ_SORTED)
