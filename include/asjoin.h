@@ -63,6 +63,12 @@ extern "C" {
                                 radix sort that reads |T| on the device (no host round trip; device
                                 scratch of 16 bytes per out_cap entry, stream-ordered).  Not
                                 supported by asj_join_batch (ASJ_EUNSUPPORTED). */
+#define ASJ_VALIDATE 0x20u    /* check on the device, before any key byte is read, that every offsets
+                                array starts at >= 0 and never decreases (R at build time, S at each
+                                probe, both relations for asj_join_batch); on a violation nothing is
+                                joined, |T| is reported as -1 (every out_count[j] for a batch) and,
+                                for a bad build relation, asj_table_status returns ASJ_EINVAL.
+                                (offsets[n] beyond the data buffer cannot be detected.) */
 #define ASJ_PROBE_SPLIT 0x8u /* probe schedule: the probe keys are signed by the signature kernel
                                 into a device scratch array first (4 bytes per key), then a probe
                                 kernel without signing walks and verifies.  Neither flag means
@@ -297,7 +303,8 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
  * The caller keeps data, offsets and out alive and unchanged until
  * asj_server_wait returns for the ticket; pinned memory (hipHostMalloc)
  * lets the copies overlap.  Returns ASJ_ENOMEM at once for a request that
- * needs more than the whole budget. */
+ * needs more than the whole budget, ASJ_EINVAL for offsets that decrease
+ * (checked on the host before anything is queued). */
 int asj_server_submit(asj_server *s, const uint8_t *data, const int64_t *offsets, int64_t n, asj_pair *out,
                       int64_t out_cap, int64_t *ticket);
 

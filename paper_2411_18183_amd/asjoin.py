@@ -30,6 +30,7 @@ ASJ_PLAIN = 0x2
 ASJ_PROBE_FUSED = 0x4
 ASJ_PROBE_SPLIT = 0x8
 ASJ_SORTED = 0x10
+ASJ_VALIDATE = 0x20
 
 
 class AsjError(RuntimeError):

@@ -142,10 +142,11 @@ int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *
 }
 
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
-                           hipStream_t st)
+                           hipStream_t st, const int32_t *status = nullptr)
 {
-    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st);
-    return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st);
+    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status);
+    return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st,
+                           status);
 }
 
 template <typename T>
@@ -190,6 +191,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->keys_per_window = kpw;
     t->split = split;
     t->sorted = (o.flags & ASJ_SORTED) != 0;
+    t->validate = (o.flags & ASJ_VALIDATE) != 0;
     t->stream = st;
     t->device = dev;
     uint32_t *sig_r = nullptr;
@@ -209,10 +211,11 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         tim_begin("table_init", st);
         le = asj_launch_fill64(t->slots, cap, ASJ_EMPTY_SLOT, st);
         if (le == hipSuccess) le = asj_launch_fill_i32(t->status, 1, 0, st);
+        if (le == hipSuccess && t->validate) le = asj_launch_validate(r->offsets, r->n, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st);
+        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, t->status);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
@@ -279,25 +282,38 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     a.plain = t->plain;
     a.verify = t->verify;
     const int mode = t->plain ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+    int32_t *pstatus = nullptr; // validation result of the probe relation
+    if (t->validate && s->n > 0) {
+        e = alloc_async(&pstatus, 1, st);
+        if (e == hipSuccess) e = asj_launch_fill_i32(pstatus, 1, 0, st);
+        if (e == hipSuccess) e = asj_launch_validate(s->offsets, s->n, pstatus, st);
+        if (e != hipSuccess) {
+            if (pstatus) (void)hipFreeAsync(pstatus, st);
+            return hip_fail(e);
+        }
+        a.probe_status = pstatus;
+    }
+    uint32_t *ssig = nullptr;
     if (!t->split || s->n == 0) {
         tim_begin(t->plain ? "hash_probe_verify" : "sign_probe_verify", st);
         e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
         tim_end(st);
-        return e == hipSuccess ? ASJ_OK : hip_fail(e);
+    } else {
+        e = alloc_async(&ssig, (size_t)s->n, st);
+        if (e == hipSuccess) {
+            tim_begin(t->plain ? "hash_S" : "sign_S", st);
+            e = launch_sign_for(s, t->sig, t->plain, ssig, g_dev[dev].tab, st, pstatus);
+            tim_end(st);
+        }
+        if (e == hipSuccess) {
+            a.ssig = ssig;
+            tim_begin(t->plain ? "hash_probe_verify" : "probe_verify", st);
+            e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+            tim_end(st);
+        }
+        if (ssig) (void)hipFreeAsync(ssig, st);
     }
-    uint32_t *ssig = nullptr;
-    e = alloc_async(&ssig, (size_t)s->n, st);
-    if (e != hipSuccess) return hip_fail(e);
-    tim_begin(t->plain ? "hash_S" : "sign_S", st);
-    e = launch_sign_for(s, t->sig, t->plain, ssig, g_dev[dev].tab, st);
-    tim_end(st);
-    if (e == hipSuccess) {
-        a.ssig = ssig;
-        tim_begin(t->plain ? "hash_probe_verify" : "probe_verify", st);
-        e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
-        tim_end(st);
-    }
-    (void)hipFreeAsync(ssig, st);
+    if (pstatus) (void)hipFreeAsync(pstatus, st);
     return e == hipSuccess ? ASJ_OK : hip_fail(e);
 }
 
@@ -350,7 +366,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
 }
 
 int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
-               int *kpw, int *split)
+               int *kpw, int *split, int *validate = nullptr)
 {
     asj_opts o = {};
     if (opts) o = *opts;
@@ -358,6 +374,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     *verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (*plain && !*verify) return ASJ_EINVAL;
     if (o.flags & ASJ_SORTED) return ASJ_EUNSUPPORTED;
+    if (validate) *validate = (o.flags & ASJ_VALIDATE) != 0;
     *sig = asj_sig_params{16, 2};
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);
@@ -512,7 +529,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split);
+    int validate;
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
@@ -546,10 +564,12 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         if (e == hipSuccess)
             e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->njoins, win_r, L.win_r_cap, win_s,
                                       L.win_s_cap, st);
+        if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
+        if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st);
+        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin("insert", st);
@@ -585,7 +605,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
         if (split && b->s.n > 0) {
             tim_begin(plain ? "hash_S" : "sign_S", st);
-            e = launch_sign_for(&b->s, sig, plain, sig_s, g_dev[dev].tab, st);
+            e = launch_sign_for(&b->s, sig, plain, sig_s, g_dev[dev].tab, st, status);
             tim_end(st);
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
             a.ssig = sig_s;

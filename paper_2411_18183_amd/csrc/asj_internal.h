@@ -178,6 +178,7 @@ struct asj_table {
     int keys_per_window; // probe keys per wave window used by probes of this table
     int split;           // probes sign the probe keys in a separate kernel first
     int sorted;          // probes sort their output pairs by (r_id, s_id)
+    int validate;        // probes check the probe relation's offsets first
     hipStream_t stream;  // build stream (orders free)
     int device;
 };
@@ -207,8 +208,11 @@ enum asj_sign_mode {
 };
 
 hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
+// status (may be NULL): device word; when it is non-zero the kernel reads no key.
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
-                           int grid_cap, hipStream_t st);
+                           int grid_cap, hipStream_t st, const int32_t *status = nullptr);
+// Sets *status = ASJ_EINVAL unless off[0] >= 0 and off[] never decreases.
+hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, hipStream_t st);
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
@@ -244,6 +248,7 @@ struct asj_probe_args {
     int64_t *out_count;
     int64_t *cand_count;
     const int32_t *table_status; // device; non-zero means the build failed
+    const int32_t *probe_status; // device or NULL; non-zero means the probe relation failed validation
     int plain;
     int verify;
     int keys_per_window; // probe keys per wave window (1..64)

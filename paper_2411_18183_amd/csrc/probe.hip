@@ -119,7 +119,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_prob
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE]; // signature accumulators, then mismatch flags
     __shared__ asj_pair kout[kWaves][kStage];   // result pairs staged before one output reservation
 
-    if (*a.table_status != 0) { // same value for every thread: the whole grid leaves
+    if (*a.table_status != 0 || (a.probe_status && *a.probe_status != 0)) { // the whole grid leaves
         if (blockIdx.x == 0) {
             if (!BATCH && threadIdx.x == 0) *a.out_count = -1;
             if (BATCH)

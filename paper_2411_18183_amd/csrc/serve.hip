@@ -383,6 +383,8 @@ int asj_server_submit(asj_server *S, const uint8_t *data, const int64_t *offsets
         return ASJ_EINVAL;
     const int64_t data_bytes = offsets[n] - offsets[0];
     if (data_bytes < 0 || (data_bytes > 0 && !data)) return ASJ_EINVAL;
+    for (int64_t k = 0; k < n; k++) // host offsets: checked here, before any copy is made from them
+        if (offsets[k + 1] < offsets[k]) return ASJ_EINVAL;
     Req *r = new (std::nothrow) Req();
     if (!r) return ASJ_ENOMEM;
     r->data = data;

@@ -43,10 +43,19 @@ __global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
 // Pass 1 (STORE = 1): row r stores itself into its home slot.  Pass 2
 // (STORE = 0): a row that lost its home slot walks on from the next slot,
 // taking the first empty one with CAS.
+// Offsets that start below zero or decrease would send the kernels outside
+// the arena; one violation anywhere marks the status word.
+__global__ void validate_kernel(const int64_t *__restrict__ off, int64_t n, int32_t *__restrict__ status)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if ((i == 0 && off[0] < 0) || off[i + 1] < off[i]) atomicExch(status, (int32_t)ASJ_EINVAL);
+}
+
 template <int PLAIN, int STORE>
 __global__ void insert_kernel(const uint32_t *__restrict__ sig, int64_t m, uint64_t *__restrict__ slots,
                               uint64_t mask, int32_t *__restrict__ status)
 {
+    if (*status != ASJ_OK) return; // validation failed: the signatures were never written
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t sg = sig[r];
         const uint64_t val = PLAIN ? (uint64_t)(uint32_t)r : (((uint64_t)sg << 32) | (uint32_t)r);
@@ -98,6 +107,13 @@ hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(validate_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, off, n, status);
     return hipGetLastError();
 }
 

@@ -316,3 +316,48 @@ def test_sorted_not_supported_for_batches(A, wl):
     R, S = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
     with pytest.raises(A.AsjError):
         A.join_batch(R, S, [0, w.R.n], [0, w.S.n], flags=A.ASJ_SORTED)
+
+
+def swapped(wl, rel, at):
+    """The relation with offsets[at] and offsets[at + 1] swapped (decreasing,
+    every offset still inside the arena)."""
+    off = rel.offsets.copy()
+    off[at], off[at + 1] = off[at + 1], off[at]
+    return wl.Relation(rel.data, off, rel.ids)
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_validate_flag(A, oracle, wl, sched):
+    import torch
+    w = wl.tiny(scale=0.3)
+    flags = A.ASJ_VALIDATE | sched_flag(A, sched)
+    # valid inputs: the output is unchanged
+    got, total, _ = gpu_join(A, w.R, w.S, flags=flags)
+    assert np.array_equal(oracle.sort_pairs(got), oracle.join_hash(w.R, w.S))
+    # a decreasing probe offset: nothing is joined, |T| = -1
+    bad_s = swapped(wl, w.S, 5)
+    Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(bad_s)
+    out = torch.empty((w.S.n, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    A.asj_join(Rk, Sk, out, cnt, flags=flags)
+    assert int(cnt[0]) == -1
+    # a decreasing build offset: the table reports ASJ_EINVAL and probes yield -1
+    t = A.asj_build(A.DeviceKeys.from_host(swapped(wl, w.R, 7)), flags=flags)
+    assert t.status() == A.ASJ_EINVAL
+    A.asj_probe(t, A.DeviceKeys.from_host(w.S), out, cnt)
+    assert int(cnt[0]) == -1
+    t.free()
+
+
+def test_validate_flag_batch(A, oracle, wl):
+    b = wl.batch(scale=0.002, njoins=6)
+    R = A.DeviceKeys.from_host(b.R)
+    S_ok = A.DeviceKeys.from_host(b.S)
+    out, oseg, counts, _, _ = A.join_batch(R, S_ok, b.r_seg, b.s_seg, flags=A.ASJ_VALIDATE)
+    outh = out.cpu().numpy()
+    for k in range(b.njoins):
+        j = b.join(k)
+        assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), oracle.join_hash(j.R, j.S))
+    S_bad = A.DeviceKeys.from_host(swapped(wl, b.S, 3))
+    _, _, counts, _, _ = A.join_batch(R, S_bad, b.r_seg, b.s_seg, flags=A.ASJ_VALIDATE)
+    assert (counts == -1).all()

@@ -92,3 +92,13 @@ def test_bad_arguments(A):
     s.close()
     with pytest.raises(A.AsjError):
         A.Server(None)  # a real server needs a table
+
+
+def test_decreasing_offsets_are_refused_at_submission(A):
+    s = A.Server(None, dry_run=True, dry_ns_per_key=1.0)
+    d, o, out = request(100)
+    o[40], o[41] = o[41], o[40]
+    with pytest.raises(A.AsjError) as e:
+        s.submit(d, o, out)
+    assert e.value.code == A.ASJ_EINVAL
+    s.close()
