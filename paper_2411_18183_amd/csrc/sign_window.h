@@ -27,8 +27,41 @@
 
 namespace asj {
 
-__device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
-__device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
+// (low half of w) << S and (high half of w) << S in one instruction each
+// (sub-dword operand select, S an inline constant); VALU only.
+template <int S>
+__device__ __forceinline__ uint32_t shl_lo16(uint32_t w)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r) : "n"(S), "v"(w));
+    return r;
+}
+template <int S>
+__device__ __forceinline__ uint32_t shl_hi16(uint32_t w)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "=v"(r) : "n"(S), "v"(w));
+    return r;
+}
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// XOR over words t = 0..T of (low symbol << STEP t) and (high symbol <<
+// STEP t + OFF): one Horner group with an unreduced accumulator.
+template <int T, int STEP, int OFF>
+__device__ __forceinline__ uint32_t fold_group(const uint32_t *w)
+{
+    if constexpr (T < 0) {
+        return 0u;
+    } else {
+        const uint32_t u = fold_group<T - 1, STEP, OFF>(w);
+        return xor3(u, shl_lo16<STEP * T>(w[T]), shl_hi16<STEP * T + OFF>(w[T]));
+    }
+}
 
 // GF(2^16): both components of one 64-byte chunk, positions relative to the
 // chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
@@ -41,12 +74,7 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
     // shifted by v stays below 2^31, plus the accumulator times x^16
 #pragma unroll
     for (int g = 1; g >= 0; g--) {
-        uint32_t u = 0;
-#pragma unroll
-        for (int t = 0; t < 8; t++) {
-            const uint32_t w = kd[8 * g + t];
-            u ^= (lo16(w) << (2 * t)) ^ (hi16(w) << (2 * t + 1));
-        }
+        const uint32_t u = fold_group<7, 2, 1>(kd + 8 * g);
         const uint32_t t1 = (a1 << 16) ^ u;
         a1 = (t1 & 0xFFFFu) ^ asj_cmul16(t1 >> 16, red);
     }
@@ -54,12 +82,7 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
         // component 2: four groups of 8 symbols; p_v shifted by 2v stays below 2^30
 #pragma unroll
         for (int q = 3; q >= 0; q--) {
-            uint32_t u = 0;
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const uint32_t w = kd[4 * q + t];
-                u ^= (lo16(w) << (4 * t)) ^ (hi16(w) << (4 * t + 2));
-            }
+            const uint32_t u = fold_group<3, 4, 2>(kd + 4 * q);
             const uint32_t t2 = (a2 << 16) ^ u;
             a2 = (t2 & 0xFFFFu) ^ asj_cmul16(t2 >> 16, red);
         }
