@@ -72,6 +72,27 @@ int64_t request_bytes(int64_t n, int64_t data_bytes, int64_t cap, int kpw)
                      al256(4 * (size_t)(n / kpw + 1)) + al256(8 * (size_t)cap) + 2048);
 }
 
+// Pinned staging a launch of K keys, J requests and W windows uses: the
+// metadata block (offsets .. window map, laid out as on the device) and the
+// counts read back.
+size_t staging_bytes(int64_t K, int64_t J, int64_t W)
+{
+    const size_t meta = al256(8 * (size_t)(K + 1)) + al256(4 * (size_t)(K > 0 ? K : 1)) +
+                        2 * al256(8 * (size_t)(J + 1)) + al256(sizeof(asj_join_desc) * (size_t)J) + 256 +
+                        al256(4 * (size_t)(W > 0 ? W : 1));
+    return al256(meta) + al256(8 * (size_t)J);
+}
+
+int grow_staging(Slot &sl, size_t bytes)
+{
+    if (sl.pin) (void)hipHostFree(sl.pin);
+    sl.pin = nullptr;
+    sl.pin_bytes = 0;
+    if (hipHostMalloc((void **)&sl.pin, bytes, hipHostMallocDefault) != hipSuccess) return ASJ_ENOMEM;
+    sl.pin_bytes = bytes;
+    return ASJ_OK;
+}
+
 } // namespace
 
 struct asj_server {
@@ -129,15 +150,11 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     const size_t o_ssig = al256(o_out + 8 * (size_t)(C > 0 ? C : 1)); // probe signatures (split schedule)
     const size_t dev_bytes = S->tbl.split ? al256(o_ssig + 4 * (size_t)(K > 0 ? K : 1)) : o_ssig;
     const size_t meta_bytes = o_cnt - o_off; // offsets .. descriptors, staged in one copy
-    // pinned staging (metadata, then the counts read back)
-    const size_t need = al256(meta_bytes) + al256(8 * (size_t)J);
-    if (sl.pin_bytes < need) {
-        if (sl.pin) (void)hipHostFree(sl.pin);
-        sl.pin = nullptr;
-        sl.pin_bytes = 0;
-        if (hipHostMalloc((void **)&sl.pin, need, hipHostMallocDefault) != hipSuccess) return ASJ_ENOMEM;
-        sl.pin_bytes = need;
-    }
+    // pinned staging (metadata, then the counts read back); sized for a full
+    // batch when the server starts, grown geometrically past that (pinning
+    // and unpinning host memory is slow and may wait for the device)
+    const size_t need = staging_bytes(K, J, W);
+    if (sl.pin_bytes < need && grow_staging(sl, std::max(need, 2 * sl.pin_bytes)) != ASJ_OK) return ASJ_ENOMEM;
     sl.counts_off = al256(meta_bytes);
     uint8_t *meta = sl.pin;
     int64_t *h_off = (int64_t *)(meta + (o_off - o_off));
@@ -363,6 +380,21 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
                 }
                 delete S;
                 return ASJ_EHIP;
+            }
+        }
+        // staging for a full batch on every slot, allocated once
+        const int kpw = t->keys_per_window >= 1 ? t->keys_per_window : ASJ_DEFAULT_KEYS_PER_WINDOW;
+        const size_t full = staging_bytes(o.max_batch_keys, o.max_batch_requests,
+                                          o.max_batch_keys / kpw + o.max_batch_requests);
+        for (Slot &sl : S->slots) {
+            if (grow_staging(sl, full) != ASJ_OK) {
+                for (Slot &x : S->slots) {
+                    if (x.pin) (void)hipHostFree(x.pin);
+                    (void)hipEventDestroy(x.ev);
+                    (void)hipStreamDestroy(x.st);
+                }
+                delete S;
+                return ASJ_ENOMEM;
             }
         }
         // the table's build must be complete before any probe on the slot streams
