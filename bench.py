@@ -346,7 +346,7 @@ def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, see
         res["load"] = f
         serial_sweep.append(res)
     serial.close()
-    need = [q.nbytes + 25 * q.n + (1 << 13) for q in payloads]  # a request's device footprint, rounded up
+    need = [q.nbytes + 26 * q.n + (1 << 13) for q in payloads]  # a request's device footprint, rounded up
     small_budget = int(max(2.0 * float(np.mean(need)), 1.1 * max(need)))
     sb = A.Server(table, slots=4, hbm_budget=small_budget)
     small, order, counts = run(sb, rate_per_s=0.7 * mu)

@@ -354,7 +354,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     L->win_r = off;
     off = align256(off + sizeof(int32_t) * (size_t)L->win_r_cap);
     L->win_s = off;
-    off = align256(off + sizeof(int32_t) * (size_t)L->win_s_cap);
+    off = align256(off + sizeof(asj_win) * (size_t)L->win_s_cap);
     L->sig = off;
     off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->ssig = off;
@@ -551,7 +551,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     uint64_t *tot = (uint64_t *)(ws + L.tot);
     int32_t *status = (int32_t *)(ws + L.status);
     int32_t *win_r = (int32_t *)(ws + L.win_r);
-    int32_t *win_s = (int32_t *)(ws + L.win_s);
+    asj_win *win_s = (asj_win *)(ws + L.win_s);
     uint32_t *sig_r = (uint32_t *)(ws + L.sig);
     uint32_t *sig_s = (uint32_t *)(ws + L.ssig);
     uint64_t *slots = (uint64_t *)(ws + L.slots);
@@ -562,8 +562,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw, desc,
                                   rows_done, b->out_count, b->cand_count, b->done_clock, tot, status, st);
         if (e == hipSuccess)
-            e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->njoins, win_r, L.win_r_cap, win_s,
-                                      L.win_s_cap, st);
+            e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw, win_r, L.win_r_cap,
+                                      win_s, L.win_s_cap, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
@@ -596,7 +596,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.njoins = b->njoins;
         a.s_seg = b->s_seg;
         a.desc = desc;
-        a.win_join = win_s;
+        a.wins = win_s;
         a.nwin = tot + 2;
         a.nwin_cap = L.win_s_cap;
         a.out_seg = b->out_seg;

@@ -224,6 +224,14 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
 // window spans two joins: join j's build rows form windows wbase_r ..
 // (64 rows each, for the inserts) and its probe rows windows wbase ..
 // (keys_per_window rows each, for the probe kernel).
+// One probe window of a batch: its join, its first probe row and how many
+// rows it holds (1 .. keys_per_window).
+struct asj_win {
+    int32_t join;
+    int32_t rows;
+    int64_t first;
+};
+
 struct asj_join_desc {
     uint64_t tbase;  // first slot of the join's segment
     uint64_t mask;   // segment capacity - 1 (a power of two minus one)
@@ -256,12 +264,11 @@ struct asj_probe_args {
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
     // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its
     // counters out_count[j], cand_count[j].  Window w (w < min(*nwin,
-    // nwin_cap)) holds the rows of join win_join[w] from s_seg[j] + (w -
-    // desc[j].wbase) * keys_per_window on.
+    // nwin_cap)) is wins[w]: rows first .. first + rows of join wins[w].join.
     int32_t njoins;
     const int64_t *s_seg;
     const asj_join_desc *desc;
-    const int32_t *win_join;
+    const asj_win *wins;
     const uint64_t *nwin;
     int64_t nwin_cap;
     const int64_t *out_seg;
@@ -287,8 +294,8 @@ hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int
                                  int64_t *rows_done, int64_t *out_count, int64_t *cand_count, uint64_t *done_clock,
                                  uint64_t *tot, int32_t *status, hipStream_t st);
 hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
-                                 int32_t njoins, int32_t *win_r, int64_t win_r_cap, int32_t *win_s, int64_t win_s_cap,
-                                 hipStream_t st);
+                                 const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
+                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, hipStream_t st);
 hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
                                    const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
                                    int32_t *status, hipStream_t st);

@@ -82,12 +82,15 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
     }
 }
 
-// Empty slots up to the planned total, then the window -> join maps (block
-// b writes the windows of joins b, b + gridDim.x, ...).  Every write stays
-// inside the caller's capacities whatever the segment arrays hold.
+// Empty slots up to the planned total, then the window maps (block b
+// writes the windows of joins b, b + gridDim.x, ...): build window -> join,
+// and for every probe window its join, first row and row count.  Every
+// write stays inside the caller's capacities whatever the segment arrays
+// hold.
 __global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap, const uint64_t *__restrict__ tot,
-                                  const asj_join_desc *__restrict__ desc, int32_t J, int32_t *__restrict__ win_r,
-                                  int64_t win_r_cap, int32_t *__restrict__ win_s, int64_t win_s_cap)
+                                  const asj_join_desc *__restrict__ desc, const int64_t *__restrict__ s_seg,
+                                  int32_t J, int kpw, int32_t *__restrict__ win_r, int64_t win_r_cap,
+                                  asj_win *__restrict__ win_s, int64_t win_s_cap)
 {
     const int64_t n = min(slot_cap, (int64_t)tot[0]);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -98,8 +101,15 @@ __global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap
         const int64_t r0 = desc[j].wbase_r, s0 = desc[j].wbase;
         const int64_t r1 = j + 1 < J ? desc[j + 1].wbase_r : nr;
         const int64_t s1 = j + 1 < J ? desc[j + 1].wbase : ns;
+        const int64_t first = s_seg[j], end = s_seg[j + 1];
         for (int64_t w = r0 + threadIdx.x; w < min(r1, nr); w += blockDim.x) win_r[w] = j;
-        for (int64_t w = s0 + threadIdx.x; w < min(s1, ns); w += blockDim.x) win_s[w] = j;
+        for (int64_t w = s0 + threadIdx.x; w < min(s1, ns); w += blockDim.x) {
+            asj_win e;
+            e.join = j;
+            e.first = first + (w - s0) * kpw;
+            e.rows = (int32_t)min((int64_t)kpw, end - e.first);
+            win_s[w] = e;
+        }
     }
 }
 
@@ -167,12 +177,12 @@ hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int
 }
 
 hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
-                                 int32_t njoins, int32_t *win_r, int64_t win_r_cap, int32_t *win_s, int64_t win_s_cap,
-                                 hipStream_t st)
+                                 const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
+                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, hipStream_t st)
 {
     const int g = grid_for(slot_cap > njoins * 256LL ? slot_cap : njoins * 256LL, 256, 16384);
-    hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, slots, slot_cap, tot, desc, njoins, win_r,
-                       win_r_cap, win_s, win_s_cap);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, slots, slot_cap, tot, desc, s_seg, njoins,
+                       keys_per_window, win_r, win_r_cap, win_s, win_s_cap);
     return hipGetLastError();
 }
 

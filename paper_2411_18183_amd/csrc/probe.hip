@@ -106,7 +106,9 @@ __device__ __forceinline__ int wave_sum(int v)
 }
 
 template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH, int PRESIGNED>
-__global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_probe_args a,
+// At most 128 registers (4 waves per SIMD): above that only one block fits a
+// CU.
+__global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_probe_args a,
                                                                          const uint16_t *__restrict__ gtab)
 {
     constexpr int kBlock = Shape<PRESIGNED>::block;
@@ -167,31 +169,64 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block) void probe_kernel(asj_prob
 
     const int kpw = a.keys_per_window;
     const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
-    for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += (int64_t)gridDim.x * kWaves) {
-        // the window's rows [k0, k1), its join and table segment
-        int64_t k0 = win * kpw, k1 = a.n;
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    // What starts the next window -- its map entry (batch), or its keys'
+    // offsets and ids (single join) -- is requested while the current window
+    // is processed, so a window does not begin with a chain of dependent
+    // loads.  Vector loads (every lane asks for the same entry), so that the
+    // requests wait in the in-order vector queue and not in the counter the
+    // LDS operations share with scalar loads.
+    asj_win pre_w = {0, 0, 0};
+    int64_t pre_o0 = 0, pre_o1 = 0;
+    int32_t pre_id = 0;
+    auto prefetch = [&](int64_t w) {
+        if (w >= nwin) return;
+        if (BATCH) {
+            pre_w = a.wins[w];
+        } else {
+            const int64_t kk = w * kpw + lane;
+            if (lane < kpw && kk < a.n) {
+                pre_o0 = a.soff[kk];
+                pre_o1 = a.soff[kk + 1];
+                pre_id = a.sids ? a.sids[kk] : (int32_t)kk;
+            }
+        }
+    };
+    prefetch((int64_t)blockIdx.x * kWaves + wave);
+    for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += stride) {
+        // the window's rows, its join and table segment
+        int64_t k0 = win * kpw;
+        int rows = (int)min((int64_t)kpw, a.n - k0);
         int j = 0;
         const uint64_t *slots = a.slots;
         uint64_t mask = a.mask;
-        if (BATCH) {
-            j = __builtin_amdgcn_readfirstlane(a.win_join[win]);
-            const asj_join_desc d = a.desc[j];
-            slots = a.slots + d.tbase;
-            mask = d.mask;
-            k0 = a.s_seg[j] + (win - d.wbase) * kpw;
-            k1 = min(a.s_seg[j + 1], a.n);
-            stage_join = j;
-        }
-        const int64_t k = k0 + lane;
-        const bool valid = lane < kpw && k >= 0 && k < k1;
         int64_t ss = 0;
         int ls = 0;
         int32_t sid = 0;
-        if (valid) {
-            ss = a.soff[k];
-            ls = (int)(a.soff[k + 1] - ss);
-            sid = a.sids ? a.sids[k] : (int32_t)k;
+        if (BATCH) {
+            j = __builtin_amdgcn_readfirstlane(pre_w.join);
+            rows = __builtin_amdgcn_readfirstlane(pre_w.rows);
+            k0 = ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(pre_w.first >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)pre_w.first);
+            const asj_join_desc d = a.desc[j];
+            slots = a.slots + d.tbase;
+            mask = d.mask;
+            stage_join = j;
         }
+        const int64_t k = k0 + lane;
+        const bool valid = lane < rows && k >= 0 && k < a.n;
+        if (BATCH) {
+            if (valid) {
+                ss = a.soff[k];
+                ls = (int)(a.soff[k + 1] - ss);
+                sid = a.sids ? a.sids[k] : (int32_t)k;
+            }
+        } else if (valid) {
+            ss = pre_o0;
+            ls = (int)(pre_o1 - pre_o0);
+            sid = pre_id;
+        }
+        prefetch(win + stride);
         uint32_t sg = 0;
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];

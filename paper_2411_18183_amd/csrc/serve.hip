@@ -69,7 +69,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t request_bytes(int64_t n, int64_t data_bytes, int64_t cap, int kpw)
 {
     return (int64_t)(al256((size_t)data_bytes) + al256(8 * (size_t)(n + 1)) + 2 * al256(4 * (size_t)n) +
-                     al256(4 * (size_t)(n / kpw + 1)) + al256(8 * (size_t)cap) + 2048);
+                     al256(sizeof(asj_win) * (size_t)(n / kpw + 1)) + al256(8 * (size_t)cap) + 2048);
 }
 
 // Pinned staging a launch of K keys, J requests and W windows uses: the
@@ -79,7 +79,7 @@ size_t staging_bytes(int64_t K, int64_t J, int64_t W)
 {
     const size_t meta = al256(8 * (size_t)(K + 1)) + al256(4 * (size_t)(K > 0 ? K : 1)) +
                         2 * al256(8 * (size_t)(J + 1)) + al256(sizeof(asj_join_desc) * (size_t)J) + 256 +
-                        al256(4 * (size_t)(W > 0 ? W : 1));
+                        al256(sizeof(asj_win) * (size_t)(W > 0 ? W : 1));
     return al256(meta) + al256(8 * (size_t)J);
 }
 
@@ -144,7 +144,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     const size_t o_desc = al256(o_oseg + 8 * (size_t)(J + 1));
     const size_t o_nwin = al256(o_desc + sizeof(asj_join_desc) * (size_t)J);
     const size_t o_win = al256(o_nwin + 8);
-    const size_t o_cnt = al256(o_win + 4 * (size_t)(W > 0 ? W : 1));
+    const size_t o_cnt = al256(o_win + sizeof(asj_win) * (size_t)(W > 0 ? W : 1));
     const size_t o_done = al256(o_cnt + 8 * (size_t)J);
     const size_t o_out = al256(o_done + 8 * (size_t)J);
     const size_t o_ssig = al256(o_out + 8 * (size_t)(C > 0 ? C : 1)); // probe signatures (split schedule)
@@ -163,7 +163,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     int64_t *h_oseg = (int64_t *)(meta + (o_oseg - o_off));
     asj_join_desc *h_desc = (asj_join_desc *)(meta + (o_desc - o_off));
     uint64_t *h_nwin = (uint64_t *)(meta + (o_nwin - o_off));
-    int32_t *h_win = (int32_t *)(meta + (o_win - o_off));
+    asj_win *h_win = (asj_win *)(meta + (o_win - o_off));
     int64_t row = 0, db = 0, ob = 0, wb = 0;
     for (int j = 0; j < J; j++) {
         const Req *r = batch[j];
@@ -174,7 +174,11 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         h_desc[j].wbase = wb;
         h_desc[j].wbase_r = 0;
         const int64_t nw = (r->n + kpw - 1) / kpw;
-        for (int64_t w = 0; w < nw; w++) h_win[wb + w] = j;
+        for (int64_t w = 0; w < nw; w++) {
+            h_win[wb + w].join = j;
+            h_win[wb + w].first = row + w * kpw;
+            h_win[wb + w].rows = (int32_t)std::min((int64_t)kpw, r->n - w * kpw);
+        }
         wb += nw;
         const int64_t base = r->off[0];
         for (int64_t k = 0; k < r->n; k++) {
@@ -223,7 +227,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.njoins = J;
         a.s_seg = (const int64_t *)(d + o_sseg);
         a.desc = (const asj_join_desc *)(d + o_desc);
-        a.win_join = (const int32_t *)(d + o_win);
+        a.wins = (const asj_win *)(d + o_win);
         a.nwin = (const uint64_t *)(d + o_nwin);
         a.nwin_cap = W;
         a.out_seg = (const int64_t *)(d + o_oseg);

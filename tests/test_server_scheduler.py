@@ -24,7 +24,7 @@ def request(n, key_len=10):
 def footprint(n, key_len=10, cap=None):
     al = lambda x: (x + 255) // 256 * 256
     cap = n if cap is None else cap
-    return al(n * key_len) + al(8 * (n + 1)) + 2 * al(4 * n) + al(4 * (n // 64 + 1)) + al(8 * cap) + 2048
+    return al(n * key_len) + al(8 * (n + 1)) + 2 * al(4 * n) + al(16 * (n // 64 + 1)) + al(8 * cap) + 2048
 
 
 def run(A, sizes, **opts):
