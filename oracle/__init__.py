@@ -202,3 +202,47 @@ def join_signature(R, S, f=16, nsym=2, verify=True, cap=None):
     pairs, _ = _run_join(lib().or_join_sig, R, S, extra_front=(f, nsym, 1 if verify else 0),
                          extra_back=(_ptr(ncand, _i64p),), cap=cap)
     return pairs, int(ncand[0])
+
+
+# ---------------------------------------------------------------------------
+# Join variants beyond the inner equi-join (the paper names outer joins and
+# the semi-join as future work, Section 5).  Each is its plain definition
+# over the inner join T (pairs of key-equal rows) and the probe relation S:
+#   semi   S |x R : one pair (-1, s_id) per probe row with at least one match
+#   anti   S |> R : one pair (-1, s_id) per probe row with no match
+#   left   S =x R : T plus (-1, s_id) for every probe row with no match
+# Matches are exact key equality (or, with verify=False, signature equality,
+# the paper-literal reading).
+# ---------------------------------------------------------------------------
+
+def _probe_ids(S):
+    _, _, ids, n = _as_rel(S)
+    return np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, dtype=np.int32)
+
+
+def _matched_rows(R, S, verify=True):
+    """Boolean per probe row: does it match some build row?  Probe row i is
+    matched exactly when it occurs in the inner join (computed with row
+    indexes as ids, so repeated ids cannot hide a row)."""
+    data, off, _, n = _as_rel(S)
+    rows = (data, off, np.arange(n, dtype=np.int32))
+    pairs = join_hash(R, rows, cap=n + 1024) if verify else join_signature(R, rows, verify=False)[0]
+    matched = np.zeros(n, dtype=bool)
+    matched[pairs[:, 1]] = True
+    return matched
+
+
+def join_variant(R, S, kind: str, verify=True):
+    """Semi ('semi'), anti ('anti') or left outer ('left') join of S with R,
+    as sorted (r_id, s_id) pairs (r_id = -1 for the probe-only rows)."""
+    ids = _probe_ids(S)
+    matched = _matched_rows(R, S, verify)
+    lonely = np.stack([np.full(int((~matched).sum()), -1, np.int32), ids[~matched]], axis=1)
+    if kind == "semi":
+        return sort_pairs(np.stack([np.full(int(matched.sum()), -1, np.int32), ids[matched]], axis=1))
+    if kind == "anti":
+        return sort_pairs(lonely)
+    if kind == "left":
+        inner = join_nested(R, S) if verify else join_signature(R, S, verify=False)[0]
+        return sort_pairs(np.concatenate([inner.reshape(-1, 2), lonely]))
+    raise ValueError(kind)

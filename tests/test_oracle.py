@@ -391,3 +391,39 @@ def test_fixed_length_workload_structure(oracle, wl):
     assert w.meta["copies"] == 400
     pairs = oracle.join_hash(w.R, w.S)
     assert len(pairs) >= 400  # every copy matches its source row (more only through equal random keys)
+
+
+def _brute_variant(R_keys, S_keys, S_ids, kind):
+    """Semi / anti / left outer join by explicit Python loops over the keys."""
+    out = []
+    for s, sid in zip(S_keys, S_ids):
+        hits = [r for r, rk in enumerate(R_keys) if rk == s]
+        if kind == "semi" and hits:
+            out.append((-1, sid))
+        elif kind in ("anti", "left") and not hits:
+            out.append((-1, sid))
+        if kind == "left":
+            out += [(r, sid) for r in hits]
+    return sorted(out)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_join_variants_equal_brute_force(oracle, wl, seed):
+    w = wl.random_small(seed, m=40 + 7 * seed, n=60 + 5 * seed, max_len=[2, 5, 9, 30, 3][seed], alphabet=b"ab\x00")
+    R_keys = [w.R.key(i) for i in range(w.R.n)]
+    S_keys = [w.S.key(i) for i in range(w.S.n)]
+    S_ids = [int(x) for x in w.S.ids]
+    for kind in ("semi", "anti", "left"):
+        got = [tuple(map(int, p)) for p in oracle.join_variant(w.R, w.S, kind)]
+        assert got == _brute_variant(R_keys, S_keys, S_ids, kind), kind
+
+
+def test_join_variant_invariants(oracle, wl):
+    w = wl.tiny(scale=0.2)
+    inner = oracle.join_hash(w.R, w.S)
+    semi, anti, left = (oracle.join_variant(w.R, w.S, k) for k in ("semi", "anti", "left"))
+    assert len(semi) + len(anti) == w.S.n                      # every probe row is in exactly one of them
+    assert not set(semi[:, 1]) & set(anti[:, 1])
+    assert set(semi[:, 1]) == set(inner[:, 1])
+    assert np.array_equal(left, oracle.sort_pairs(np.concatenate([inner, anti])))
+    assert len(semi) == 400 and (semi[:, 0] == -1).all()      # the recipe's copies are the matches
