@@ -69,6 +69,18 @@ extern "C" {
                                 joined, |T| is reported as -1 (every out_count[j] for a batch) and,
                                 for a bad build relation, asj_table_status returns ASJ_EINVAL.
                                 (offsets[n] beyond the data buffer cannot be detected.) */
+/* Join kind (at most one; none = the inner equi-join of Section 2 / 3.2).
+ * The paper names outer joins and the semi-join as future work (Section 5);
+ * here they are of the probe relation S with the build relation R, and a
+ * probe-only row is reported as the pair (-1, s_id):
+ *   ASJ_SEMI        S semi-join R: (-1, s_id) once per probe row with a match
+ *   ASJ_ANTI        S anti-join R: (-1, s_id) for each probe row without one
+ *   ASJ_LEFT_OUTER  every inner pair plus (-1, s_id) for each unmatched row
+ * |T| counts the pairs written.  A match is key equality, or signature
+ * equality under ASJ_NO_VERIFY.  More than one kind: ASJ_EINVAL. */
+#define ASJ_SEMI 0x40u
+#define ASJ_ANTI 0x80u
+#define ASJ_LEFT_OUTER 0x100u
 #define ASJ_PROBE_SPLIT 0x8u /* probe schedule: the probe keys are signed by the signature kernel
                                 into a device scratch array first (4 bytes per key), then a probe
                                 kernel without signing walks and verifies.  Neither flag means

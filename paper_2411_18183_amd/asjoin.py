@@ -31,6 +31,9 @@ ASJ_PROBE_FUSED = 0x4
 ASJ_PROBE_SPLIT = 0x8
 ASJ_SORTED = 0x10
 ASJ_VALIDATE = 0x20
+ASJ_SEMI = 0x40
+ASJ_ANTI = 0x80
+ASJ_LEFT_OUTER = 0x100
 
 
 class AsjError(RuntimeError):

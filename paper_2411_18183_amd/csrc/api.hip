@@ -120,6 +120,15 @@ int resolve_sig(asj_sig_params p, asj_sig_params *out)
     return ASJ_EUNSUPPORTED;
 }
 
+// Join kind from the flags; -1 when more than one is set.
+int join_kind(uint32_t flags)
+{
+    const int n = ((flags & ASJ_SEMI) != 0) + ((flags & ASJ_ANTI) != 0) + ((flags & ASJ_LEFT_OUTER) != 0);
+    if (n > 1) return -1;
+    return (flags & ASJ_SEMI) ? ASJ_KIND_SEMI : (flags & ASJ_ANTI) ? ASJ_KIND_ANTI
+                              : (flags & ASJ_LEFT_OUTER) ? ASJ_KIND_LEFT : ASJ_KIND_INNER;
+}
+
 // Table load factor, probe keys per window and probe schedule (1 = split:
 // sign kernel, then a probe kernel with the stored signatures; 0 = fused)
 // for options that may leave them to the library: a value the caller set
@@ -166,6 +175,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     const int plain = (o.flags & ASJ_PLAIN) != 0;
     const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (plain && !verify) return ASJ_EINVAL; // the plain table has no signature to trust
+    if (join_kind(o.flags) < 0) return ASJ_EINVAL;
     asj_sig_params sig = {16, 2};
     if (!plain) {
         int rc = resolve_sig(o.sig, &sig);
@@ -192,6 +202,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->split = split;
     t->sorted = (o.flags & ASJ_SORTED) != 0;
     t->validate = (o.flags & ASJ_VALIDATE) != 0;
+    t->kind = join_kind(o.flags);
     t->stream = st;
     t->device = dev;
     uint32_t *sig_r = nullptr;
@@ -281,6 +292,7 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     a.table_status = t->status;
     a.plain = t->plain;
     a.verify = t->verify;
+    a.kind = t->kind;
     const int mode = t->plain ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
     int32_t *pstatus = nullptr; // validation result of the probe relation
     if (t->validate && s->n > 0) {
@@ -366,7 +378,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
 }
 
 int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
-               int *kpw, int *split, int *validate = nullptr)
+               int *kpw, int *split, int *validate = nullptr, int *kind = nullptr)
 {
     asj_opts o = {};
     if (opts) o = *opts;
@@ -375,6 +387,9 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     if (*plain && !*verify) return ASJ_EINVAL;
     if (o.flags & ASJ_SORTED) return ASJ_EUNSUPPORTED;
     if (validate) *validate = (o.flags & ASJ_VALIDATE) != 0;
+    const int k = join_kind(o.flags);
+    if (k < 0) return ASJ_EINVAL;
+    if (kind) *kind = k;
     *sig = asj_sig_params{16, 2};
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);
@@ -529,8 +544,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int validate;
-    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate);
+    int validate, kind;
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
@@ -593,6 +608,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.table_status = status;
         a.plain = plain;
         a.verify = verify;
+        a.kind = kind;
         a.njoins = b->njoins;
         a.s_seg = b->s_seg;
         a.desc = desc;

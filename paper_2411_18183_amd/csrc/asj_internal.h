@@ -179,6 +179,7 @@ struct asj_table {
     int split;           // probes sign the probe keys in a separate kernel first
     int sorted;          // probes sort their output pairs by (r_id, s_id)
     int validate;        // probes check the probe relation's offsets first
+    int kind;            // ASJ_KIND_*
     hipStream_t stream;  // build stream (orders free)
     int device;
 };
@@ -224,6 +225,9 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
 // window spans two joins: join j's build rows form windows wbase_r ..
 // (64 rows each, for the inserts) and its probe rows windows wbase ..
 // (keys_per_window rows each, for the probe kernel).
+// Join kinds (the flags ASJ_SEMI, ASJ_ANTI, ASJ_LEFT_OUTER).
+enum { ASJ_KIND_INNER = 0, ASJ_KIND_SEMI = 1, ASJ_KIND_ANTI = 2, ASJ_KIND_LEFT = 3 };
+
 // One probe window of a batch: its join, its first probe row and how many
 // rows it holds (1 .. keys_per_window).
 struct asj_win {
@@ -260,6 +264,7 @@ struct asj_probe_args {
     int plain;
     int verify;
     int keys_per_window; // probe keys per wave window (1..64)
+    int kind;            // ASJ_KIND_*: inner, semi, anti or left outer join of the probe relation
     // batch of joins (njoins > 0): probe row k belongs to join j with
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
     // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its

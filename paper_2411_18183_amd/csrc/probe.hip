@@ -167,6 +167,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         nstage = 0;
     };
 
+    const bool pairs_out = a.kind == ASJ_KIND_INNER || a.kind == ASJ_KIND_LEFT; // the matching pairs themselves
     const int kpw = a.keys_per_window;
     const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
     const int64_t stride = (int64_t)gridDim.x * kWaves;
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         wk.qb = ~0ull;
         wk.walking = valid;
         int lane_cand = 0;
+        bool matched = false; // this lane's key has a verified (or, unverified, signature-equal) match
         for (;;) {
             uint32_t r = 0;
             const bool has = next_candidate<PLAIN>(slots, mask, sg, wk, r);
@@ -316,10 +318,25 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
                 asj_wave_sync();
             }
             // stage the survivors in LDS; output space is reserved per flush
-            const uint64_t m = __ballot(ok);
-            if (ok) {
+            matched = matched || ok;
+            const bool emit = ok && pairs_out;
+            const uint64_t m = __ballot(emit);
+            if (emit) {
                 asj_pair p;
                 p.r_id = a.rids ? a.rids[r] : (int32_t)r;
+                p.s_id = sid;
+                wout[nstage + __popcll(m & lanemask_lt)] = p;
+            }
+            nstage += __popcll(m);
+            if (nstage > kStage - ASJ_WAVE) flush();
+        }
+        if (a.kind != ASJ_KIND_INNER) {
+            // semi: matched probe rows; anti and left outer: unmatched ones
+            const bool emit = valid && (a.kind == ASJ_KIND_SEMI ? matched : !matched);
+            const uint64_t m = __ballot(emit);
+            if (emit) {
+                asj_pair p;
+                p.r_id = -1;
                 p.s_id = sid;
                 wout[nstage + __popcll(m & lanemask_lt)] = p;
             }

@@ -224,6 +224,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.table_status = S->tbl.status;
         a.plain = S->tbl.plain;
         a.verify = S->tbl.verify;
+        a.kind = S->tbl.kind;
         a.njoins = J;
         a.s_seg = (const int64_t *)(d + o_sseg);
         a.desc = (const asj_join_desc *)(d + o_desc);

@@ -361,3 +361,58 @@ def test_validate_flag_batch(A, oracle, wl):
     S_bad = A.DeviceKeys.from_host(swapped(wl, b.S, 3))
     _, _, counts, _, _ = A.join_batch(R, S_bad, b.r_seg, b.s_seg, flags=A.ASJ_VALIDATE)
     assert (counts == -1).all()
+
+
+KINDS = {"semi": 0x40, "anti": 0x80, "left": 0x100}
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+@pytest.mark.parametrize("kind", sorted(KINDS))
+def test_join_variants_equal_oracle(A, oracle, wl, kind, sched):
+    """Semi, anti and left outer joins of the probe relation: exact pair
+    multisets against the oracle's definitions, with the signature join, the
+    plain join and the paper-literal (unverified) match."""
+    for seed in range(3):
+        w = wl.random_small(seed, m=150 + 40 * seed, n=300, max_len=[2, 9, 70][seed], alphabet=b"ab\x00")
+        got, total, _ = gpu_join(A, w.R, w.S, sched=sched, flags=KINDS[kind])
+        want = oracle.join_variant(w.R, w.S, kind)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), seed
+        got, total, _ = gpu_join(A, w.R, w.S, sched=sched, flags=KINDS[kind] | A.ASJ_PLAIN)
+        assert np.array_equal(oracle.sort_pairs(got), want), seed
+        got, total, _ = gpu_join(A, w.R, w.S, sched=sched, flags=KINDS[kind] | A.ASJ_NO_VERIFY)
+        assert np.array_equal(oracle.sort_pairs(got), oracle.join_variant(w.R, w.S, kind, verify=False)), seed
+    t = wl.tiny(scale=0.5)
+    got, total, _ = gpu_join(A, t.R, t.S, sched=sched, flags=KINDS[kind] | A.ASJ_SORTED)
+    assert np.array_equal(got, oracle.join_variant(t.R, t.S, kind))  # sorted on the device
+
+
+def test_join_variants_batch_and_served(A, oracle, wl):
+    import torch
+    b = wl.batch(scale=0.002, njoins=8)
+    R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
+    for kind in ("anti", "left"):
+        caps = 2 * np.diff(b.s_seg) + 16
+        out, oseg, counts, _, _ = A.join_batch(R, S, b.r_seg, b.s_seg, caps=caps, flags=KINDS[kind])
+        outh = out.cpu().numpy()
+        for k in range(b.njoins):
+            j = b.join(k)
+            assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]),
+                                  oracle.join_variant(j.R, j.S, kind)), (kind, k)
+    Rs = wl.served_build_side(scale=0.002)
+    t = A.asj_build(A.DeviceKeys.from_host(Rs), flags=A.ASJ_SEMI)
+    srv = A.Server(t, slots=2)
+    reqs = [wl.served_request(Rs, seed=5, request=i, min_size=300, max_size=3000) for i in range(4)]
+    bufs = [(torch.from_numpy(q.data).pin_memory(), torch.from_numpy(q.offsets).pin_memory(),
+             torch.empty((q.n, 2), dtype=torch.int32).pin_memory()) for q in reqs]
+    infos = [srv.wait(srv.submit(d, o, out)) for d, o, out in bufs]
+    srv.close()
+    for q, x, (_, _, out) in zip(reqs, infos, bufs):
+        assert x["status"] == 0
+        assert np.array_equal(oracle.sort_pairs(out[:x["count"]].numpy()), oracle.join_variant(Rs, q, "semi"))
+    t.free()
+
+
+def test_two_join_kinds_rejected(A, wl):
+    w = wl.random_small(1, m=10, n=10)
+    with pytest.raises(A.AsjError):
+        gpu_join(A, w.R, w.S, flags=KINDS["semi"] | KINDS["anti"])
