@@ -5,7 +5,9 @@
 
 namespace {
 
-constexpr int kBlock = 512;
+// 16 waves per block: one LDS copy of the GF tables (35 KB) serves twice as
+// many waves, so two blocks (32 waves) fit a CU instead of three blocks of 8.
+constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / ASJ_WAVE;
 
 template <int MODE, int NSYM>
