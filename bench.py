@@ -250,6 +250,32 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     }
 
 
+def bench_tiny_latency(A, torch, W, runs: int = 1000):
+    """Latency of one whole tiny join (R = S = 10k keys of 256 B): HIP events
+    around each of `runs` calls (the inputs stay resident; the 6 MB of keys
+    are cache-resident, which is why the batched form is the throughput
+    figure for this workload)."""
+    import numpy as np
+    w = W.tiny()
+    Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
+    out = torch.empty((w.S.n, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    for _ in range(20):
+        A.asj_join(Rk, Sk, out, cnt)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        A.asj_join(Rk, Sk, out, cnt)
+        e1.record()
+    torch.cuda.synchronize()
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    assert int(cnt[0]) == w.meta["expected_matches"]
+    return {"runs": runs, "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_ms": round(float(lat.mean()), 4),
+            "workload": "one tiny join (R = S = 10k keys of 256 B, 2000 matches) per call, inputs resident"}
+
+
 def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096),
                        probe_bytes: int = 1 << 29):
     """Signature join vs plain byte-compare hash join on keys of one length
@@ -455,6 +481,24 @@ def main():
                   + 8 * tab_cap + 8 * w.R.n + 8 * w.S.n + 8 * n_pairs)
     step_gbps = step_bytes / (ms_step * 1e-3) / 1e9
 
+    # the plain streaming read rate on this part (the library's read kernel
+    # over the probe key arena), so the roofline can also be read against
+    # what a kernel that only reads reaches
+    word = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nbytes_read = int(w.S.nbytes) // 16 * 16
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    A.asj_util_read(Sk.data, nbytes_read, word)
+    ev0.record()
+    for _ in range(5):
+        A.asj_util_read(Sk.data, nbytes_read, word)
+    ev1.record()
+    torch.cuda.synchronize()
+    read_gbps = nbytes_read * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    roofline["stream_read_gbps"] = round(read_gbps, 1)
+    roofline["frac_of_stream_read"] = round(achieved / read_gbps, 4)
+    if traffic:
+        roofline["traffic_gbps"] = round(traffic / (phase_ms[dominant] * 1e-3) / 1e9, 1)
+
     plain = None
     if not args.no_plain:
         counts_p = torch.zeros(2, dtype=torch.int64, device="cuda")
@@ -488,6 +532,9 @@ def main():
         batched["workload"] = (f"batch of 256 joins at {args.batch_scale:g} scale: |R_j| log-uniform 100-200k, "
                                f"|S_j| = U(1,8)|R_j|, XML-like keys log-uniform 16-2048 B, 25% copies")
         log(f"batch: {batched}")
+    tiny_single = bench_tiny_latency(A, torch, W) if args.tiny_instances > 0 else None
+    if tiny_single:
+        log(f"tiny single-join latency: {tiny_single}")
     tiny_batch = None
     if args.tiny_instances > 0:
         tw = tiny_instances(W, args.tiny_instances)
@@ -512,8 +559,13 @@ def main():
         t = time.perf_counter()
         cp, _ = O.join_signature(ws.R, ws.S)
         dt = time.perf_counter() - t
+        t = time.perf_counter()
+        cpp = O.join_hash(ws.R, ws.S, cap=len(cp) + 1024)
+        dt_plain = time.perf_counter() - t
+        assert len(cpp) == len(cp)
         cpu = {"value": round(ws.S.n / dt, 1), "unit": "probe tuples/s", "cores": 1, "kind": "oracle",
                "seconds": round(dt, 2),
+               "plain_hash_join_value": round(ws.S.n / dt_plain, 1), "plain_hash_join_seconds": round(dt_plain, 2),
                "sample": f"{args.workload} recipe at {args.scale * args.cpu_scale:g} scale (R={ws.R.n}, S={ws.S.n}, "
                          f"{ws.R.nbytes + ws.S.nbytes} key bytes); single-threaded C oracle signature join "
                          f"with byte verification; |T|={len(cp)}",
@@ -545,6 +597,7 @@ def main():
         "plain_hash_join": plain,
         "batched": batched,
         "tiny_batched": tiny_batch,
+        "tiny_single_join_latency": tiny_single,
         "served": served,
         "autotune": tune,
         "length_sweep": sweep,
