@@ -482,19 +482,24 @@ def main():
     step_gbps = step_bytes / (ms_step * 1e-3) / 1e9
 
     # the plain streaming read rate on this part (the library's read kernel
-    # over the probe key arena), so the roofline can also be read against
-    # what a kernel that only reads reaches
+    # over the probe key arena, best of three grid sizes), so the roofline
+    # can also be read against what a kernel that only reads reaches
     word = torch.zeros(1, dtype=torch.int32, device="cuda")
     nbytes_read = int(w.S.nbytes) // 16 * 16
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    A.asj_util_read(Sk.data, nbytes_read, word)
-    ev0.record()
-    for _ in range(5):
-        A.asj_util_read(Sk.data, nbytes_read, word)
-    ev1.record()
-    torch.cuda.synchronize()
-    read_gbps = nbytes_read * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    read_gbps, read_grid = 0.0, 0
+    for grid in (2048, 8192, 32768):
+        A.asj_util_read(Sk.data, nbytes_read, word, grid=grid)
+        ev0.record()
+        for _ in range(5):
+            A.asj_util_read(Sk.data, nbytes_read, word, grid=grid)
+        ev1.record()
+        torch.cuda.synchronize()
+        gbps = nbytes_read * 5 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        if gbps > read_gbps:
+            read_gbps, read_grid = gbps, grid
     roofline["stream_read_gbps"] = round(read_gbps, 1)
+    roofline["stream_read_grid"] = read_grid
     roofline["frac_of_stream_read"] = round(achieved / read_gbps, 4)
     if traffic:
         roofline["traffic_gbps"] = round(traffic / (phase_ms[dominant] * 1e-3) / 1e9, 1)
