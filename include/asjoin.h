@@ -232,6 +232,75 @@ int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_pro
 
 int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream);
 
+/* ---- relations in host memory, beyond the device memory a call may use ---- */
+
+/* Options of asj_join_host.
+ *   hbm_budget  device bytes the call may hold at once (0: 80% of the free
+ *               device memory).
+ *   partitions  0: chosen by the library (1 while the build side and its
+ *               table fit half the budget, else the smallest power of two
+ *               whose partitions fit); else a power of two 1 .. 1024. */
+typedef struct asj_host_opts {
+    int64_t hbm_budget;
+    int32_t partitions;
+    int32_t reserved; /* 0 */
+} asj_host_opts;
+
+/* What asj_join_host did (all filled on ASJ_OK). */
+typedef struct asj_host_stats {
+    int32_t partitions;   /* 1: build side resident, probe side streamed */
+    int32_t reserved;
+    int64_t chunks;       /* host-to-device chunks in the partitioning pass (0 when partitions = 1) */
+    int64_t pieces;       /* probe launches (one per piece of the probe side) */
+    int64_t bytes_h2d;    /* bytes copied host -> device */
+    int64_t bytes_d2h;    /* bytes copied device -> host */
+    int64_t device_peak;  /* most device bytes held at once */
+    double ms_partition;  /* host wall time of the partitioning pass */
+    double ms_join;       /* host wall time of building and probing */
+} asj_host_stats;
+
+/* Join relations held in host memory (pinned memory gives the full host
+ * link rate; pageable memory works), for build sides larger than the device
+ * memory the call may use: the Grace hash join of Section 2 on one GPU, with
+ * the signature as the partitioning hash.
+ *   partitions = 1: R is copied to the device whole, signed and built once
+ *     (Section 3.2, Figure 2); S streams through in pieces that fit the
+ *     budget, each probed as asj_probe does, two pieces in flight.
+ *   partitions P > 1: a partitioning pass streams R, then S, through the
+ *     device in chunks; each key is signed and moved to partition
+ *     mix32(signature) >> (32 - log2 P) (equal keys, and keys of equal
+ *     signature, share a partition: Section 2's bucket property), and the
+ *     partitioned chunks go back to library-owned pinned host memory with
+ *     their signatures.  Then, per partition, R_p is copied in and inserted
+ *     from its stored signatures, and the pieces of S_p are probed against
+ *     it without signing again.  Host-link traffic: 3|R| + 3|S| bytes of keys
+ *     plus 16 bytes per key each way (Section 4.1 counts the same three
+ *     passes over each relation for its disk buckets).
+ * Arguments:
+ *   r, s       relations with HOST pointers (data, offsets, ids as in
+ *              asj_keys; ids == NULL means the row index).
+ *   opts       join options as for asj_join; ASJ_SORTED: ASJ_EUNSUPPORTED;
+ *              the offsets are always checked on the host (ASJ_EINVAL).
+ *   hopts      NULL = all defaults.
+ *   out        HOST array of out_cap pairs (may be NULL when out_cap = 0);
+ *              the first min(|T|, out_cap) pairs, in no particular order.
+ *   out_count  HOST int64: |T| (all pairs, also those beyond out_cap).
+ *   stats      NULL or filled as above.
+ *   stream     device work is ordered after the stream's earlier work;
+ *              the call returns when everything is done (it synchronizes).
+ * Errors: ASJ_EINVAL (arguments, offsets), ASJ_ENOMEM (the budget cannot
+ * hold one key with its buffers, a partition of R too large for the budget
+ * even at 1024 partitions -- heavy duplicates -- or one probe row with more
+ * pairs than a piece's output buffer), ASJ_ETABLEFULL, ASJ_EHIP. */
+int asj_join_host(const asj_keys *r, const asj_keys *s, const asj_opts *opts, const asj_host_opts *hopts,
+                  asj_pair *out, int64_t out_cap, int64_t *out_count, asj_host_stats *stats, hipStream_t stream);
+
+/* asj_join_host keeps the pinned host regions of its last partitioned join
+ * (about |R| + |S| key bytes plus 16 bytes per key) for the next call; this
+ * frees them.  Calls made while another asj_join_host runs use private
+ * regions instead.  Returns ASJ_OK. */
+int asj_join_host_release(void);
+
 /* ---- autotuning ---- */
 
 /* Outcome of an autotuning run. */

@@ -68,6 +68,16 @@ class asj_tune_result(ctypes.Structure):
                 ("trials", ctypes.c_int32)]
 
 
+class asj_host_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("partitions", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class asj_host_stats(ctypes.Structure):
+    _fields_ = [("partitions", ctypes.c_int32), ("reserved", ctypes.c_int32), ("chunks", ctypes.c_int64),
+                ("pieces", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64),
+                ("device_peak", ctypes.c_int64), ("ms_partition", ctypes.c_double), ("ms_join", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -101,11 +111,14 @@ def lib():
                                          ctypes.POINTER(asj_tune_result), P]
         L.asj_autotune_clear.argtypes = []
         L.asj_autotune_clear.restype = None
+        L.asj_join_host.argtypes = [ctypes.POINTER(asj_keys), ctypes.POINTER(asj_keys), ctypes.POINTER(asj_opts),
+                                    ctypes.POINTER(asj_host_opts), P, I64, P, ctypes.POINTER(asj_host_stats), P]
+        L.asj_join_host_release.argtypes = []
         L.asj_clock_khz.argtypes = []
         L.asj_clock_khz.restype = I64
         for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_table_status", "asj_table_free",
                      "asj_timing_enable", "asj_timing_read", "asj_util_copy", "asj_join_batch", "asj_autotune",
-                     "asj_autotune_batch"):
+                     "asj_autotune_batch", "asj_join_host", "asj_join_host_release"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,6 +254,63 @@ def join(R: DeviceKeys, S: DeviceKeys, cap: Optional[int] = None, **kw):
         asj_join(R, S, out, counts, **kw)
         total, ncand = (int(x) for x in counts.tolist())
     return out[:max(total, 0)], total, ncand
+
+
+@dataclass
+class HostKeys:
+    """A relation's join attributes in host memory (CPU tensors; pinned ones
+    give asj_join_host the full host-link rate)."""
+    data: torch.Tensor              # uint8
+    offsets: torch.Tensor           # int64, n + 1
+    ids: Optional[torch.Tensor]     # int32, n (None -> row index)
+
+    @property
+    def n(self) -> int:
+        return self.offsets.numel() - 1
+
+    @classmethod
+    def from_host(cls, rel, pin=True, with_ids=True) -> "HostKeys":
+        """Wrap (and by default pin) a host relation's numpy data/offsets/ids."""
+        def t(a):
+            x = torch.from_numpy(a)
+            return x.pin_memory() if pin else x
+        ids = t(rel.ids) if (with_ids and rel.ids is not None) else None
+        return cls(t(rel.data), t(rel.offsets), ids)
+
+    def c(self) -> asj_keys:
+        for t, dt in ((self.data, torch.uint8), (self.offsets, torch.int64)):
+            if t.dtype != dt or t.is_cuda or not t.is_contiguous():
+                raise ValueError("host keys: data must be contiguous cpu uint8, offsets contiguous cpu int64")
+        if self.ids is not None and (self.ids.dtype != torch.int32 or self.ids.is_cuda or
+                                     not self.ids.is_contiguous() or self.ids.numel() != self.n):
+            raise ValueError("host keys: ids must be a contiguous cpu int32 tensor of n elements")
+        return asj_keys(self.data.data_ptr() if self.data.numel() else None, self.offsets.data_ptr(),
+                        self.ids.data_ptr() if self.ids is not None else None, self.n)
+
+
+def asj_join_host(R: HostKeys, S: HostKeys, out: torch.Tensor, f: int = 16, nsym: int = 2,
+                  load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, hbm_budget: int = 0,
+                  partitions: int = 0, stream=None):
+    """Join host-resident relations within a device-memory budget.  out: cpu int32 [cap, 2].
+    Returns (|T|, stats dict); the first min(|T|, cap) rows of out hold pairs."""
+    if out.is_cuda or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous cpu int32 tensor [cap, 2]")
+    kr, ks = R.c(), S.c()
+    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    ho = asj_host_opts(int(hbm_budget), int(partitions), 0)
+    st = asj_host_stats()
+    cnt = ctypes.c_int64(0)
+    cap = out.shape[0]
+    _check(lib().asj_join_host(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o), ctypes.byref(ho),
+                               ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.byref(cnt),
+                               ctypes.byref(st), _stream(stream)), "asj_join_host")
+    stats = {name: getattr(st, name) for name, _ in asj_host_stats._fields_ if name != "reserved"}
+    return int(cnt.value), stats
+
+
+def asj_join_host_release():
+    """Free the pinned host regions asj_join_host keeps between calls."""
+    _check(lib().asj_join_host_release(), "asj_join_host_release")
 
 
 def timing_enable(on: bool = True):

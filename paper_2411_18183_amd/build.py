@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libasjoin.so")
-SOURCES = ["gf_tables.hip", "sign.hip", "table.hip", "probe.hip", "batch.hip", "serve.hip", "util.hip", "tune.hip", "sort.hip", "api.hip"]
+SOURCES = ["gf_tables.hip", "sign.hip", "table.hip", "probe.hip", "batch.hip", "serve.hip", "util.hip", "tune.hip", "sort.hip", "stream.hip", "api.hip"]
 ARCH = "gfx950"
 
 

@@ -400,6 +400,23 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
 
 } // namespace
 
+int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r)
+{
+    asj_opts o = {};
+    if (opts) o = *opts;
+    r->plain = (o.flags & ASJ_PLAIN) != 0;
+    r->verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    if (r->plain && !r->verify) return ASJ_EINVAL;
+    r->kind = join_kind(o.flags);
+    if (r->kind < 0) return ASJ_EINVAL;
+    r->sig = asj_sig_params{16, 2};
+    if (!r->plain) {
+        const int rc = resolve_sig(o.sig, &r->sig);
+        if (rc != ASJ_OK) return rc;
+    }
+    return resolve_auto(0, n_build, o, &r->lf, &r->kpw, &r->split);
+}
+
 const uint16_t *asj_device_tables(int *dev)
 {
     int d = 0;

@@ -195,6 +195,17 @@ struct asj_tuned {
 bool asj_tuned_lookup(int batch, int64_t n_build, const asj_opts &o, asj_tuned *t);
 void asj_tuned_store(int batch, int64_t n_build, const asj_opts &o, const asj_tuned &t);
 
+// Join options resolved as asj_build resolves them (signature parameters,
+// plain / verify, join kind, and load factor, keys per window and schedule
+// from the caller, else the autotuner's record, else the defaults) for a
+// build side of n_build rows.
+struct asj_resolved {
+    asj_sig_params sig;
+    int plain, verify, kind, split, kpw;
+    float lf;
+};
+int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r);
+
 // GF constant tables of the current device (initialising the library on
 // first use); nullptr on failure.
 const uint16_t *asj_device_tables(int *dev);

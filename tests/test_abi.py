@@ -62,3 +62,46 @@ def test_invalid_arguments_are_rejected_before_any_device_work(lib):
     assert lib.asj_autotune_batch(None, None, None, None) == -1
     lib.asj_autotune_clear.restype = None
     lib.asj_autotune_clear()
+
+
+class _Keys(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_int32), ("nsym", ctypes.c_int32), ("load_factor", ctypes.c_float),
+                ("flags", ctypes.c_uint32), ("keys_per_window", ctypes.c_int32)]
+
+
+class _HostOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("partitions", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def test_host_join_checks_its_arguments_on_the_host(lib):
+    """asj_join_host validates pointers, host offsets, partition counts and flags before any device work."""
+    f = lib.asj_join_host
+    f.restype = ctypes.c_int
+    data = (ctypes.c_uint8 * 8)(*b"abcdefgh")
+    good = (ctypes.c_int64 * 3)(0, 4, 8)
+    bad = (ctypes.c_int64 * 3)(0, 6, 4)  # decreasing
+    cnt = ctypes.c_int64(-7)
+    out = (ctypes.c_int32 * 8)()
+    R = _Keys(ctypes.cast(data, ctypes.c_void_p), ctypes.cast(good, ctypes.c_void_p), None, 2)
+    Sbad = _Keys(ctypes.cast(data, ctypes.c_void_p), ctypes.cast(bad, ctypes.c_void_p), None, 2)
+    P = ctypes.byref
+    # missing out_count, negative capacity, capacity without a buffer
+    assert f(P(R), P(R), None, None, out, ctypes.c_int64(4), None, None, None) == -1
+    assert f(P(R), P(R), None, None, out, ctypes.c_int64(-1), P(cnt), None, None) == -1
+    assert f(P(R), P(R), None, None, None, ctypes.c_int64(4), P(cnt), None, None) == -1
+    # offsets that decrease, a NULL relation
+    assert f(P(R), P(Sbad), None, None, out, ctypes.c_int64(4), P(cnt), None, None) == -1
+    assert f(None, P(R), None, None, out, ctypes.c_int64(4), P(cnt), None, None) == -1
+    # partitions must be 0 or a power of two up to 1024; the budget must not be negative
+    for parts, budget in ((3, 0), (2048, 0), (-1, 0), (0, -5)):
+        ho = _HostOpts(budget, parts, 0)
+        assert f(P(R), P(R), None, P(ho), out, ctypes.c_int64(4), P(cnt), None, None) == -1
+    # sorted output is not offered for host joins
+    o = _Opts(16, 2, 0.0, 0x10, 0)
+    assert f(P(R), P(R), P(o), None, out, ctypes.c_int64(4), P(cnt), None, None) == -6
+    assert cnt.value == -7  # never written on a rejected call
