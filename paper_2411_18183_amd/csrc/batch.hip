@@ -126,29 +126,33 @@ __global__ void insert_batch_kernel(const uint32_t *__restrict__ sig, int64_t m,
 {
     if (*status != ASJ_OK) return; // same value for every thread
     const int64_t nw = min(win_cap, (int64_t)tot[1]);
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nw * ASJ_WAVE;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t w = t / ASJ_WAVE;
-        const int j = win_r[w];
-        const asj_join_desc d = desc[j];
-        const int64_t g = r_seg[j] + (w - d.wbase_r) * ASJ_WAVE + (t % ASJ_WAVE);
-        if (g < 0 || g >= r_seg[j + 1] || g >= m) continue;
+    const int lane = threadIdx.x % ASJ_WAVE;
+    const int wpb = blockDim.x / ASJ_WAVE;
+    // a window of 64 build rows is one wave's work, so its join, segment
+    // and table descriptor are wave-uniform values
+    for (int64_t w = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x / ASJ_WAVE); w < nw;
+         w += (int64_t)gridDim.x * wpb) {
+        const int j = __builtin_amdgcn_readfirstlane(win_r[w]);
+        const int64_t lo = r_seg[j], hi = min(r_seg[j + 1], m);
+        const uint64_t tbase = desc[j].tbase, mask = desc[j].mask;
+        const int64_t g = lo + (w - desc[j].wbase_r) * ASJ_WAVE + lane;
+        if (g < lo || g >= hi) continue;
         const uint32_t sg = sig[g];
         const uint64_t val = ((uint64_t)sg << 32) | (uint32_t)g;
-        uint64_t h = asj_mix32(sg) & d.mask;
+        uint64_t h = asj_mix32(sg) & mask;
         if (STORE) {
-            slots[d.tbase + h] = val;
+            slots[tbase + h] = val;
             continue;
         }
-        if (slots[d.tbase + h] == val) continue;
+        if (slots[tbase + h] == val) continue;
         uint64_t tries = 0;
         for (;;) {
-            h = (h + 1) & d.mask;
-            if (++tries > d.mask) {
+            h = (h + 1) & mask;
+            if (++tries > mask) {
                 atomicExch(status, (int32_t)ASJ_ETABLEFULL);
                 break;
             }
-            const uint64_t old = atomicCAS((unsigned long long *)&slots[d.tbase + h],
+            const uint64_t old = atomicCAS((unsigned long long *)&slots[tbase + h],
                                            (unsigned long long)ASJ_EMPTY_SLOT, (unsigned long long)val);
             if (old == ASJ_EMPTY_SLOT) break;
         }
