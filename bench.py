@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--serve-arrivals", type=int, default=48)
     ap.add_argument("--length-sweep", action="store_true",
                     help="also time signature vs plain joins on keys of one length, 4 B .. 4 KB")
+    ap.add_argument("--host-budget", type=int, default=1 << 30, metavar="BYTES",
+                    help="device budget of the partitioned host-memory join (0: skip the host-memory joins)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -309,6 +311,41 @@ def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 
     return rows
 
 
+def bench_host(A, torch, w, expected: int, budget: int, Sk, runs: int = 2):
+    """asj_join_host on the same relations held in pinned host memory: R
+    resident with S streamed (default budget), and the partitioned join
+    within `budget` device bytes.  Host-link-inclusive rates."""
+    Rh, Sh = A.HostKeys.from_host(w.R), A.HostKeys.from_host(w.S)
+    out = torch.empty((expected + 1024, 2), dtype=torch.int32).pin_memory()
+    # the host link's own rate: pinned -> device copy of the probe key arena
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    Sk.data.copy_(Sh.data, non_blocking=True)
+    e0.record()
+    Sk.data.copy_(Sh.data, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    h2d_gbps = Sh.data.numel() / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    res = {"workload": "the main line's relations in pinned host memory", "pinned_h2d_gbps": round(h2d_gbps, 1)}
+    for name, b in (("resident_build", 0), ("partitioned", budget)):
+        A.asj_join_host(Rh, Sh, out, hbm_budget=b)  # warm-up (pins the library's host regions)
+        times, st, total = [], None, 0
+        for _ in range(runs):
+            t = time.perf_counter()
+            total, st = A.asj_join_host(Rh, Sh, out, hbm_budget=b)
+            times.append(time.perf_counter() - t)
+        sec = sorted(times)[len(times) // 2]
+        link = st["bytes_h2d"] + st["bytes_d2h"]
+        res[name] = {"budget_bytes": b if b else "80% of free device memory", "partitions": st["partitions"],
+                     "ms": round(sec * 1e3, 2), "probe_tuples_s": round(w.S.n / sec, 1),
+                     "link_bytes": link, "link_gbps": round(link / sec / 1e9, 1),
+                     "ms_partition": round(st["ms_partition"], 2), "ms_join": round(st["ms_join"], 2),
+                     "chunks": st["chunks"], "pieces": st["pieces"], "device_peak_bytes": st["device_peak"],
+                     "pairs_match_expected": total == expected}
+        log(f"host join {name}: {res[name]}")
+    A.asj_join_host_release()
+    return res
+
+
 def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, seed: int = 5):
     """Continuous-batching server over a resident build table, Poisson arrivals."""
     import numpy as np
@@ -527,6 +564,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy kernel over {nb} bytes done")
 
+    host = None
+    if args.host_budget > 0:
+        host = bench_host(A, torch, w, expected, args.host_budget, Sk)
     batched = None
     if args.batch_scale > 0:
         t = time.perf_counter()
@@ -603,6 +643,7 @@ def main():
         "batched": batched,
         "tiny_batched": tiny_batch,
         "tiny_single_join_latency": tiny_single,
+        "host_memory_join": host,
         "served": served,
         "autotune": tune,
         "length_sweep": sweep,

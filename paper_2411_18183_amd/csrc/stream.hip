@@ -36,6 +36,7 @@ constexpr int64_t kMaxChunkKeys = 1 << 22;  // keys per partitioning chunk (pack
 constexpr int kByteBits = 40;               // per-partition counters: keys << 40 | bytes
 constexpr unsigned long long kByteMask = (1ull << kByteBits) - 1;
 constexpr int kGridCap = 256 * 16;
+constexpr int64_t kMaxPieceBytes = 128ll << 20; // probe piece input (keys + 16 bytes per key)
 constexpr int64_t kPerKeyBytes = 24;        // device bytes per key beside its key bytes (offset, id, signature, move)
 
 size_t al(size_t x) { return ((x ? x : 1) + 255) & ~(size_t)255; }
@@ -210,7 +211,7 @@ struct HostChunk {
     int32_t *ids = nullptr;
     uint32_t *sig = nullptr;
     int64_t n = 0, nbytes = 0;
-    std::vector<int64_t> info; // 4 per partition: first key, keys, first byte, bytes
+    int64_t *info = nullptr; // pinned, 4 per partition: first key, keys, first byte, bytes
     HostRel rel() const
     {
         HostRel h;
@@ -335,9 +336,9 @@ int store_arena(Ctx &c, HostStore &s, int which, size_t size)
     return ASJ_OK;
 }
 
-size_t chunk_host_bytes(int64_t keys, int64_t bytes)
+size_t chunk_host_bytes(int64_t keys, int64_t bytes, int P)
 {
-    return al((size_t)bytes + 16) + al(8 * (size_t)(keys + 1)) + 2 * al(4 * (size_t)keys + 4);
+    return al((size_t)bytes + 16) + al(8 * (size_t)(keys + 1)) + 2 * al(4 * (size_t)keys + 4) + al(32 * (size_t)P);
 }
 
 int64_t rows_bytes(const HostRel &h, int64_t a, int64_t b) { return h.off[b] - h.off[a]; }
@@ -403,77 +404,136 @@ hipError_t sign_rel(Ctx &c, const DevRel &d, int64_t n, hipStream_t st)
 }
 
 // ---- partitioning pass ----
+// Two lanes (stream + buffers) take alternate chunks, so that one chunk's
+// grouped output goes back to the host while the next chunk comes in.
+struct Lane {
+    DevRel in, grp;
+    int64_t *dpos = nullptr, *info = nullptr;
+    unsigned long long *cnt = nullptr, *cursor = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+};
+
+int open_lane(Ctx &c, Lane &l, int64_t mk, int64_t mb, int P, hipEvent_t after)
+{
+    int rc = alloc_rel(c, l.in, mk, mb);
+    if (rc == ASJ_OK) rc = alloc_rel(c, l.grp, mk, mb);
+    if (rc == ASJ_OK) rc = dalloc(c, (void **)&l.dpos, 8 * (size_t)mk);
+    if (rc == ASJ_OK) rc = dalloc(c, (void **)&l.cnt, 8 * (size_t)P);
+    if (rc == ASJ_OK) rc = dalloc(c, (void **)&l.cursor, 8 * (size_t)P);
+    if (rc == ASJ_OK) rc = dalloc(c, (void **)&l.info, 32 * (size_t)P);
+    if (rc != ASJ_OK) return rc;
+    hipError_t e = hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&l.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamWaitEvent(l.st, after, 0);
+    return from_hip(e);
+}
+
+void close_lane(Ctx &c, Lane &l, int64_t mk, int P)
+{
+    if (l.st) (void)hipStreamSynchronize(l.st);
+    free_rel(c, l.in);
+    free_rel(c, l.grp);
+    dfree(c, l.dpos, 8 * (size_t)mk);
+    dfree(c, l.cnt, 8 * (size_t)P);
+    dfree(c, l.cursor, 8 * (size_t)P);
+    dfree(c, l.info, 32 * (size_t)P);
+    if (l.ev) (void)hipEventDestroy(l.ev);
+    if (l.st) (void)hipStreamDestroy(l.st);
+    l = Lane();
+}
+
+// Signs and groups rows [a, b) of h on lane l and copies the grouped chunk
+// into hc's pinned region; completion is l.ev.
+int partition_chunk(Ctx &c, Lane &l, const HostRel &h, int64_t a, int64_t b, int logp, HostChunk &hc)
+{
+    const int P = 1 << logp;
+    const int64_t nk = b - a, nb = rows_bytes(h, a, b);
+    int rc = load_rows(c, h, a, b, l.in, 0, 0, l.st);
+    if (rc != ASJ_OK) return rc;
+    hipError_t e = sign_rel(c, l.in, nk, l.st);
+    if (e == hipSuccess) e = asj_launch_fill_i64((int64_t *)l.cnt, P, 0, l.st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(part_hist_kernel, dim3(grid_for(nk, 256)), dim3(256), 0, l.st, l.in.sig, l.in.off, nk, logp,
+                           l.cnt);
+        hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, l.st, l.cnt, logp, l.cursor, l.info, l.grp.off,
+                           nk);
+        hipLaunchKernelGGL(part_scatter_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, l.st, l.in.sig,
+                           l.in.off, l.in.ids, nk, logp, l.cursor, l.grp.sig, l.grp.ids, l.grp.off, l.dpos);
+        hipLaunchKernelGGL(part_move_kernel, dim3(grid_for(nk, 4)), dim3(256), 0, l.st, l.in.bytes, l.in.off, l.dpos,
+                           nk, l.grp.bytes);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && nb > 0) e = hipMemcpyAsync(hc.bytes, l.grp.bytes, (size_t)nb, hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.off, l.grp.off, 8 * (size_t)(nk + 1), hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.ids, l.grp.ids, 4 * (size_t)nk, hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.sig, l.grp.sig, 4 * (size_t)nk, hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.info, l.info, 32 * (size_t)P, hipMemcpyDeviceToHost, l.st);
+    if (e == hipSuccess) e = hipEventRecord(l.ev, l.st);
+    c.stats.bytes_d2h += nb + 16 * nk + 8 + 32 * P;
+    c.stats.chunks++;
+    l.busy = true;
+    return from_hip(e);
+}
+
+int lane_wait(Lane &l)
+{
+    if (!l.busy) return ASJ_OK;
+    l.busy = false;
+    return from_hip(hipEventSynchronize(l.ev));
+}
+
 int partition_rel(Ctx &c, const HostRel &h, int logp, HostStore &store, int which)
 {
     const int P = 1 << logp;
     std::vector<Range> ranges;
-    // input and grouped copies of a chunk share the budget (a quarter kept for the counters and slack)
-    const int64_t cost = std::max<int64_t>(c.budget * 3 / 8 - 4096, 1);
+    // two lanes, each with an input and a grouped copy of its chunk, share
+    // three quarters of the budget
+    const int64_t cost = std::max<int64_t>(c.budget * 3 / 16 - 4096, 1);
     int rc = split_rows(&h, 0, h.n, kMaxChunkKeys, kPerKeyBytes, cost, ranges);
     if (rc != ASJ_OK) return rc;
-    int64_t mk = 0, mb = 0;
+    int64_t mk = 1, mb = 1;
     size_t host = 0;
     for (const Range &r : ranges) {
         mk = std::max(mk, r.b - r.a);
         mb = std::max(mb, rows_bytes(h, r.a, r.b));
-        host += chunk_host_bytes(r.b - r.a, rows_bytes(h, r.a, r.b));
+        host += chunk_host_bytes(r.b - r.a, rows_bytes(h, r.a, r.b), P);
     }
     store.chunks.clear();
     rc = store_arena(c, store, which, host);
     if (rc != ASJ_OK) return rc;
+    // carve every chunk's pinned region up front
     size_t carve = 0;
-    DevRel in, grp;
-    int64_t *dpos = nullptr, *info = nullptr;
-    unsigned long long *cnt = nullptr, *cursor = nullptr;
-    rc = alloc_rel(c, in, mk, mb);
-    if (rc == ASJ_OK) rc = alloc_rel(c, grp, mk, mb);
-    if (rc == ASJ_OK) rc = dalloc(c, (void **)&dpos, 8 * (size_t)mk);
-    if (rc == ASJ_OK) rc = dalloc(c, (void **)&cnt, 8 * (size_t)P);
-    if (rc == ASJ_OK) rc = dalloc(c, (void **)&cursor, 8 * (size_t)P);
-    if (rc == ASJ_OK) rc = dalloc(c, (void **)&info, 32 * (size_t)P);
-    for (size_t i = 0; rc == ASJ_OK && i < ranges.size(); i++) {
-        const int64_t a = ranges[i].a, b = ranges[i].b, nk = b - a, nb = rows_bytes(h, a, b);
-        rc = load_rows(c, h, a, b, in, 0, 0, c.st);
-        if (rc != ASJ_OK) break;
-        hipError_t e = sign_rel(c, in, nk, c.st);
-        if (e == hipSuccess) e = asj_launch_fill_i64((int64_t *)cnt, P, 0, c.st);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(part_hist_kernel, dim3(grid_for(nk, 256)), dim3(256), 0, c.st, in.sig, in.off, nk,
-                               logp, cnt);
-            hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, c.st, cnt, logp, cursor, info, grp.off, nk);
-            if (nk > 0)
-                hipLaunchKernelGGL(part_scatter_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c.st,
-                                   in.sig, in.off, in.ids, nk, logp, cursor, grp.sig, grp.ids, grp.off, dpos);
-            hipLaunchKernelGGL(part_move_kernel, dim3(grid_for(nk, 4)), dim3(256), 0, c.st, in.bytes, in.off, dpos,
-                               nk, grp.bytes);
-            e = hipGetLastError();
-        }
+    for (const Range &r : ranges) {
         HostChunk hc;
-        hc.n = nk;
-        hc.nbytes = nb;
-        hc.info.resize(4 * (size_t)P);
+        hc.n = r.b - r.a;
+        hc.nbytes = rows_bytes(h, r.a, r.b);
         hc.bytes = store.arena + carve;
-        hc.off = (int64_t *)(hc.bytes + al((size_t)nb + 16));
-        hc.ids = (int32_t *)((uint8_t *)hc.off + al(8 * (size_t)(nk + 1)));
-        hc.sig = (uint32_t *)((uint8_t *)hc.ids + al(4 * (size_t)nk + 4));
-        carve += chunk_host_bytes(nk, nb);
-        if (e == hipSuccess && nb > 0) e = hipMemcpyAsync(hc.bytes, grp.bytes, (size_t)nb, hipMemcpyDeviceToHost, c.st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hc.off, grp.off, 8 * (size_t)(nk + 1), hipMemcpyDeviceToHost, c.st);
-        if (e == hipSuccess && nk > 0) e = hipMemcpyAsync(hc.ids, grp.ids, 4 * (size_t)nk, hipMemcpyDeviceToHost, c.st);
-        if (e == hipSuccess && nk > 0) e = hipMemcpyAsync(hc.sig, grp.sig, 4 * (size_t)nk, hipMemcpyDeviceToHost, c.st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hc.info.data(), info, 32 * (size_t)P, hipMemcpyDeviceToHost, c.st);
-        if (e == hipSuccess) e = hipStreamSynchronize(c.st);
-        c.stats.bytes_d2h += nb + 16 * nk + 8 + 32 * P;
-        c.stats.chunks++;
+        hc.off = (int64_t *)(hc.bytes + al((size_t)hc.nbytes + 16));
+        hc.ids = (int32_t *)((uint8_t *)hc.off + al(8 * (size_t)(hc.n + 1)));
+        hc.sig = (uint32_t *)((uint8_t *)hc.ids + al(4 * (size_t)hc.n + 4));
+        hc.info = (int64_t *)((uint8_t *)hc.sig + al(4 * (size_t)hc.n + 4));
+        carve += chunk_host_bytes(hc.n, hc.nbytes, P);
         store.chunks.push_back(hc);
-        rc = from_hip(e);
     }
-    free_rel(c, in);
-    free_rel(c, grp);
-    dfree(c, dpos, 8 * (size_t)mk);
-    dfree(c, cnt, 8 * (size_t)P);
-    dfree(c, cursor, 8 * (size_t)P);
-    dfree(c, info, 32 * (size_t)P);
+    hipEvent_t start = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(start, c.st); // after the caller's earlier work on its stream
+    rc = from_hip(e);
+    Lane lanes[2];
+    for (int i = 0; rc == ASJ_OK && i < 2 && i < (int)ranges.size(); i++) rc = open_lane(c, lanes[i], mk, mb, P, start);
+    for (size_t i = 0; rc == ASJ_OK && i < ranges.size(); i++) {
+        Lane &l = lanes[i & 1];
+        rc = lane_wait(l);
+        if (rc == ASJ_OK) rc = partition_chunk(c, l, h, ranges[i].a, ranges[i].b, logp, store.chunks[i]);
+    }
+    for (int i = 0; i < 2; i++) {
+        const int r2 = lane_wait(lanes[i]);
+        if (rc == ASJ_OK) rc = r2;
+        close_lane(c, lanes[i], mk, P);
+    }
+    if (start) (void)hipEventDestroy(start);
     return rc;
 }
 
@@ -698,7 +758,9 @@ int plan_slots(Ctx &c, int64_t left, const std::vector<Range> &in, std::vector<R
                int64_t *bytes, int64_t *out_cap)
 {
     const int64_t per_slot = left / 2 - 4096;
-    const int64_t input = per_slot / 4 * 3;
+    // pieces of at most kMaxPieceBytes keep the two slots alternating (one
+    // piece's copy in while the other is probed) and their buffers small
+    const int64_t input = std::min<int64_t>(per_slot / 4 * 3, kMaxPieceBytes);
     *out_cap = std::max<int64_t>(1, (per_slot - input) / 8 - 64);
     if (input <= 1024) return ASJ_ENOMEM;
     for (const Range &r : in) {

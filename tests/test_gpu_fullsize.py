@@ -138,3 +138,24 @@ def test_full_size_served_requests_equal_oracle(A, oracle, wl):
         assert np.array_equal(oracle.sort_pairs(got), oracle.sort_pairs(sel)), i
         assert unique_pairs(got), i
     t.free()
+
+
+def test_full_size_host_join_partitioned_equals_oracle(A, oracle, wl):
+    """The large join (4.9 GB of keys) from pinned host memory within a 1 GiB
+    device budget, the benchmark's partitioned configuration: the build side
+    does not fit half the budget, so both relations are partitioned by
+    signature bits; the output must be the oracle's whole join."""
+    import torch
+    w = wl.large()
+    expected = int(w.meta["expected_matches"])
+    note(f"host join: R={w.R.n} S={w.S.n}, 1 GiB budget")
+    Rh, Sh = A.HostKeys.from_host(w.R), A.HostKeys.from_host(w.S)
+    out = torch.empty((expected + 1024, 2), dtype=torch.int32)
+    total, st = A.asj_join_host(Rh, Sh, out, hbm_budget=1 << 30)
+    note(f"host join: |T|={total} stats={st}")
+    assert st["partitions"] >= 2 and st["device_peak"] <= 1 << 30
+    got = out[:total].numpy()
+    want = oracle.join_hash(w.R, w.S, cap=expected + 1024)
+    assert total == len(want) == expected
+    assert np.array_equal(oracle.sort_pairs(got), want)
+    A.asj_join_host_release()
