@@ -107,8 +107,15 @@ typedef struct asj_pair {
 } asj_pair;
 
 /* Signature parameters (Section 3.1): symbol width f in bits and the number
- * of components n; f * nsym <= 32.  Supported: {16, 2} (the paper's 4-byte
- * sig_alpha,2 over GF(2^16), the default), {16, 1}, {8, 4}, {8, 2}. */
+ * of components n.  Supported: {16, 2} (the paper's 4-byte sig_alpha,2 over
+ * GF(2^16), the default), {16, 1}, {8, 4}, {8, 2}, and {16, 4}: an 8-byte
+ * signature (every change of up to four symbols detected, Section 3.1).
+ * With {16, 4} the table slot holds the low word (components 1 and 2, i.e.
+ * the {16, 2} signature) and the table keeps the high word of every build
+ * row beside it; a candidate matches both.  {16, 4} is offered by
+ * asj_signature, asj_build / asj_probe / asj_join and asj_autotune with the
+ * fused probe schedule (ASJ_PROBE_SPLIT: ASJ_EUNSUPPORTED); asj_join_batch,
+ * asj_join_host and the server return ASJ_EUNSUPPORTED for it. */
 typedef struct asj_sig_params {
     int32_t f;
     int32_t nsym;
@@ -139,8 +146,9 @@ typedef struct asj_table asj_table;
 /* Algebraic signature of every key (Section 3.1).
  *   keys     the relation (device arrays, see asj_keys)
  *   p        signature parameters; {0,0} means {16,2}
- *   sig_out  device uint32[keys->n]; component j is stored in bits
- *            [(j-1)f, jf): for {16,2}, sig = s1 | s2 << 16
+ *   sig_out  device uint32[keys->n] (uint32[2 keys->n] for {16,4}: one
+ *            little-endian 64-bit signature per key); component j is stored
+ *            in bits [(j-1)f, jf): for {16,2}, sig = s1 | s2 << 16
  * Errors: ASJ_EINVAL (null/negative), ASJ_EUNSUPPORTED (parameters),
  * ASJ_EHIP (launch). */
 int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hipStream_t stream);

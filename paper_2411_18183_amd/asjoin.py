@@ -171,9 +171,11 @@ class DeviceKeys:
 
 def asj_signature(keys: DeviceKeys, f: int = 16, nsym: int = 2, out: Optional[torch.Tensor] = None,
                   stream=None) -> torch.Tensor:
-    """Signatures of every key (int32 tensor holding the uint32 bit patterns)."""
+    """Signatures of every key (int32 tensor holding the uint32 bit patterns;
+    2 words per key, the low word first, for 64-bit signatures f * nsym = 64)."""
     if out is None:
-        out = torch.empty(max(keys.n, 0), dtype=torch.int32, device=keys.offsets.device)
+        words = 2 if f * nsym == 64 else 1
+        out = torch.empty(max(keys.n, 0) * words, dtype=torch.int32, device=keys.offsets.device)
     k = keys.c()
     _check(lib().asj_signature(ctypes.byref(k), asj_sig_params(f, nsym),
                                ctypes.c_void_p(out.data_ptr() if out.numel() else None), _stream(stream)),

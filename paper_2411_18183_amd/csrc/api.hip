@@ -107,7 +107,7 @@ bool keys_ok(const asj_keys *k)
 int resolve_sig(asj_sig_params p, asj_sig_params *out)
 {
     if (p.f == 0 && p.nsym == 0) p = asj_sig_params{16, 2};
-    if (p.f == 16 && (p.nsym == 1 || p.nsym == 2)) {
+    if (p.f == 16 && (p.nsym == 1 || p.nsym == 2 || p.nsym == 4)) {
         *out = p;
         return ASJ_OK;
     }
@@ -116,7 +116,7 @@ int resolve_sig(asj_sig_params p, asj_sig_params *out)
         return ASJ_OK;
     }
     if (p.f != 8 && p.f != 16) return ASJ_EINVAL;
-    if (p.nsym < 1 || p.f * p.nsym > 32) return ASJ_EINVAL;
+    if (p.nsym < 1 || p.f * p.nsym > 64) return ASJ_EINVAL;
     return ASJ_EUNSUPPORTED;
 }
 
@@ -150,13 +150,17 @@ int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *
     return ASJ_OK;
 }
 
+// out_hi / stride: see asj_launch_sign (four GF(2^16) components only).
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
-                           hipStream_t st, const int32_t *status = nullptr)
+                           hipStream_t st, const int32_t *status = nullptr, uint32_t *out_hi = nullptr,
+                           int stride = 1)
 {
     if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status);
     return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st,
-                           status);
+                           status, out_hi, stride);
 }
+
+bool sig64(asj_sig_params s) { return s.f == 16 && s.nsym == 4; }
 
 template <typename T>
 hipError_t alloc_async(T **p, size_t count, hipStream_t st)
@@ -184,6 +188,11 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     float lf;
     int kpw, split;
     if (resolve_auto(0, r->n, o, &lf, &kpw, &split) != ASJ_OK) return ASJ_EINVAL;
+    const bool wide = !plain && sig64(sig);
+    if (wide) { // 64-bit signatures: the fused probe schedule only
+        if (o.flags & ASJ_PROBE_SPLIT) return ASJ_EUNSUPPORTED;
+        split = 0;
+    }
     int dev = 0;
     int rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
@@ -209,10 +218,12 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     hipError_t e = alloc_async(&t->slots, (size_t)cap, st);
     if (e == hipSuccess) e = alloc_async(&t->status, 1, st);
     if (e == hipSuccess) e = alloc_async(&sig_r, (size_t)r->n, st);
+    if (e == hipSuccess && wide) e = alloc_async(&t->sig_hi, (size_t)r->n, st);
     if (e != hipSuccess) {
         if (t->slots) (void)hipFreeAsync(t->slots, st);
         if (t->status) (void)hipFreeAsync(t->status, st);
         if (sig_r) (void)hipFreeAsync(sig_r, st);
+        if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, st);
         free(t);
         return hip_fail(e);
     }
@@ -226,7 +237,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, t->status);
+        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
@@ -238,6 +249,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     if (out_rc != ASJ_OK) {
         (void)hipFreeAsync(t->slots, st);
         (void)hipFreeAsync(t->status, st);
+        if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, st);
         free(t);
         return out_rc;
     }
@@ -285,6 +297,7 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     a.n = s->n;
     a.slots = t->slots;
     a.mask = (uint64_t)t->capacity - 1;
+    a.rsig_hi = t->sig_hi;
     a.out = out;
     a.cap = out_cap;
     a.out_count = out_count;
@@ -334,6 +347,7 @@ int table_free_impl(asj_table *t)
     if (!t) return ASJ_OK;
     hipError_t e1 = hipFreeAsync(t->slots, t->stream);
     hipError_t e2 = hipFreeAsync(t->status, t->stream);
+    if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, t->stream);
     free(t);
     return (e1 == hipSuccess && e2 == hipSuccess) ? ASJ_OK : ASJ_EHIP;
 }
@@ -394,6 +408,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     if (!*plain) {
         int rc = resolve_sig(o.sig, sig);
         if (rc != ASJ_OK) return rc;
+        if (sig64(*sig)) return ASJ_EUNSUPPORTED; // 64-bit signatures: single joins only
     }
     return resolve_auto(1, n_build, o, lf, kpw, split);
 }
@@ -413,6 +428,7 @@ int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r)
     if (!r->plain) {
         const int rc = resolve_sig(o.sig, &r->sig);
         if (rc != ASJ_OK) return rc;
+        if (sig64(r->sig)) return ASJ_EUNSUPPORTED; // 64-bit signatures: asj_join / asj_probe only
     }
     return resolve_auto(0, n_build, o, &r->lf, &r->kpw, &r->split);
 }
@@ -437,7 +453,10 @@ int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hip
     int dev = 0;
     rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
-    TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st));
+    if (sig64(sig)) // little-endian 64-bit signatures: the low word, then the high word
+        TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st, nullptr, sig_out + 1, 2));
+    else
+        TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st));
     return ASJ_OK;
 }
 

@@ -175,6 +175,7 @@ struct asj_table {
     int plain;           // baseline table (no signature stored)
     int verify;          // probe compares key bytes of candidates
     asj_sig_params sig;  // signature parameters of the build
+    uint32_t *sig_hi;    // four GF(2^16) components: the build rows' high words (the slots hold the low words)
     int keys_per_window; // probe keys per wave window used by probes of this table
     int split;           // probes sign the probe keys in a separate kernel first
     int sorted;          // probes sort their output pairs by (r_id, s_id)
@@ -221,8 +222,12 @@ enum asj_sign_mode {
 
 hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
 // status (may be NULL): device word; when it is non-zero the kernel reads no key.
+// out[k * stride] = signature (plain hash) of key k; with four GF(2^16)
+// components that is the low word (components 1, 2) and out_hi[k * stride]
+// receives the high word (components 3, 4).
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
-                           int grid_cap, hipStream_t st, const int32_t *status = nullptr);
+                           int grid_cap, hipStream_t st, const int32_t *status = nullptr,
+                           uint32_t *out_hi = nullptr, int stride = 1);
 // Sets *status = ASJ_EINVAL unless off[0] >= 0 and off[] never decreases.
 hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, hipStream_t st);
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
@@ -264,6 +269,7 @@ struct asj_probe_args {
     const int32_t *sids;
     int64_t n;
     const uint32_t *ssig; // signatures (plain hashes) of the probe keys, or NULL to sign them in the kernel
+    const uint32_t *rsig_hi; // four GF(2^16) components: high words (components 3, 4) of the build rows
     const uint64_t *slots;
     uint64_t mask;
     asj_pair *out;

@@ -113,12 +113,16 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
 {
     constexpr int kBlock = Shape<PRESIGNED>::block;
     constexpr int kWaves = Shape<PRESIGNED>::waves;
+    // four GF(2^16) components: the table holds the low word (components 1,
+    // 2), a candidate must also match the build row's high word
+    constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4 && !PRESIGNED;
     __shared__ uint16_t tab[PRESIGNED ? 2 : asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];  // probe key starts
     __shared__ int64_t krs[kWaves][ASJ_WAVE];  // candidate build key starts
     __shared__ int32_t kln[kWaves][ASJ_WAVE];  // key lengths
     __shared__ int32_t kex[kWaves][ASJ_WAVE];  // exclusive prefix of chunk counts
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE]; // signature accumulators, then mismatch flags
+    __shared__ uint32_t kacc2[kHi ? kWaves : 1][ASJ_WAVE]; // high-word accumulators
     __shared__ asj_pair kout[kWaves][kStage];   // result pairs staged before one output reservation
 
     if (*a.table_status != 0 || (a.probe_status && *a.probe_status != 0)) { // the whole grid leaves
@@ -228,11 +232,11 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
             sid = pre_id;
         }
         prefetch(win + stride);
-        uint32_t sg = 0;
+        uint32_t sg = 0, sg_hi = 0;
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];
         } else {
-            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab);
+            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab, kacc2[kHi ? wave : 0], sg_hi);
         }
 
         Walk wk;
@@ -243,10 +247,12 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         bool matched = false; // this lane's key has a verified (or, unverified, signature-equal) match
         for (;;) {
             uint32_t r = 0;
-            const bool has = next_candidate<PLAIN>(slots, mask, sg, wk, r);
-            const uint64_t hm = __ballot(has);
+            const bool walked = next_candidate<PLAIN>(slots, mask, sg, wk, r);
+            const uint64_t hm = __ballot(walked);
             if (hm == 0) break;
-            wave_cand += __popcll(hm);
+            bool has = walked;
+            if (kHi && has) has = a.rsig_hi[r] == sg_hi;
+            wave_cand += __popcll(kHi ? __ballot(has) : hm);
             lane_cand += has ? 1 : 0;
 
             bool ok = has;
@@ -393,6 +399,10 @@ hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, cons
     asj_probe_args fixed = *a_in;
     if (fixed.keys_per_window < 1 || fixed.keys_per_window > ASJ_WAVE) fixed.keys_per_window = ASJ_WAVE;
     const asj_probe_args *a = &fixed;
+    if (nsym == 4 && mode == ASJ_MODE_SIG16) { // 64-bit signatures: fused schedule only
+        if (a->ssig || !a->rsig_hi) return hipErrorInvalidValue;
+        return launch_sig<ASJ_MODE_SIG16, 4>(a, tab, grid_cap, st);
+    }
     if (a->ssig) { // signatures (or plain hashes) of the probe keys are given: no signing, no tables
         if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1, 1>(a, tab, grid_cap, st);
         return a->verify ? launch<ASJ_MODE_SIG16, 2, 0, 1, 1>(a, tab, grid_cap, st)

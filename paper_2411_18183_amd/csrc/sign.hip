@@ -10,17 +10,22 @@ namespace {
 constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / ASJ_WAVE;
 
+// out[k * stride] = signature of key k (its low word with four GF(2^16)
+// components, whose high word goes to out_hi[k * stride]).
 template <int MODE, int NSYM>
 __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
                                                       const int64_t *__restrict__ off, int64_t n,
-                                                      uint32_t *__restrict__ out, const uint16_t *__restrict__ gtab,
+                                                      uint32_t *__restrict__ out, uint32_t *__restrict__ out_hi,
+                                                      int stride, const uint16_t *__restrict__ gtab,
                                                       const int32_t *__restrict__ status)
 {
+    constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
     if (status && *status != 0) return; // the inputs failed validation: read no key (same for every thread)
     __shared__ uint16_t tab[asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
     __shared__ int32_t kex[kWaves][ASJ_WAVE];
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE];
+    __shared__ uint32_t kacc2[kHi ? kWaves : 1][ASJ_WAVE];
     asj::load_tables<MODE, kBlock>(tab, gtab);
 
     const int wave = threadIdx.x / ASJ_WAVE;
@@ -34,34 +39,48 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
             s = off[k];
             len = (int)(off[k + 1] - s);
         }
-        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, kst[wave], kex[wave], kacc[wave], tab);
-        if (k < n) out[k] = v;
+        uint32_t hi = 0;
+        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, kst[wave], kex[wave], kacc[wave], tab,
+                                                        kacc2[kHi ? wave : 0], hi);
+        if (k < n) {
+            out[k * stride] = v;
+            if (kHi) out_hi[k * stride] = hi;
+        }
     }
 }
 
 template <int MODE, int NSYM>
-hipError_t launch(const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap, const int32_t *status,
-                  hipStream_t st)
+hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride, const uint16_t *tab, int grid_cap,
+                  const int32_t *status, hipStream_t st)
 {
     const int64_t nwin = (k->n + ASJ_WAVE - 1) / ASJ_WAVE;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((sign_kernel<MODE, NSYM>), dim3((unsigned)blocks), dim3(kBlock), 0, st, k->data, k->offsets,
-                       k->n, out, tab, status);
+                       k->n, out, out_hi, stride, tab, status);
     return hipGetLastError();
 }
 
 } // namespace
 
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap,
-                           hipStream_t st, const int32_t *status)
+                           hipStream_t st, const int32_t *status, uint32_t *out_hi, int stride)
 {
     if (k->n == 0) return hipSuccess;
-    if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch<ASJ_MODE_SIG16, 2>(k, out, tab, grid_cap, status, st);
-    if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch<ASJ_MODE_SIG16, 1>(k, out, tab, grid_cap, status, st);
-    if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch<ASJ_MODE_SIG8, 4>(k, out, tab, grid_cap, status, st);
-    if (mode == ASJ_MODE_SIG8 && nsym == 2) return launch<ASJ_MODE_SIG8, 2>(k, out, tab, grid_cap, status, st);
-    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, tab, grid_cap, status, st);
+    if (stride < 1) return hipErrorInvalidValue;
+    if (mode == ASJ_MODE_SIG16 && nsym == 4) {
+        if (!out_hi) return hipErrorInvalidValue;
+        return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, st);
+    }
+    if (mode == ASJ_MODE_SIG16 && nsym == 2)
+        return launch<ASJ_MODE_SIG16, 2>(k, out, nullptr, stride, tab, grid_cap, status, st);
+    if (mode == ASJ_MODE_SIG16 && nsym == 1)
+        return launch<ASJ_MODE_SIG16, 1>(k, out, nullptr, stride, tab, grid_cap, status, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 4)
+        return launch<ASJ_MODE_SIG8, 4>(k, out, nullptr, stride, tab, grid_cap, status, st);
+    if (mode == ASJ_MODE_SIG8 && nsym == 2)
+        return launch<ASJ_MODE_SIG8, 2>(k, out, nullptr, stride, tab, grid_cap, status, st);
+    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, nullptr, stride, tab, grid_cap, status, st);
     return hipErrorInvalidValue;
 }

@@ -12,7 +12,7 @@
 // scales the partial to the chunk's position in the key and XORs it (GF
 // addition) into the key's accumulator in LDS.
 //
-// Chunk arithmetic (GF(2^16), components j = 1, 2).  Component j of a chunk
+// Chunk arithmetic (GF(2^16), components j = 1 .. 4).  Component j of a chunk
 // is sum_u p_u alpha^(j u) over its 32 symbols.  Instead of one log/antilog
 // multiplication per symbol, the lane runs Horner's rule over groups of
 // symbols with an unreduced accumulator: shifting by one bit is
@@ -21,6 +21,11 @@
 // folded back with two byte-indexed table lookups (T[b] = b x^16).  Scaling
 // a chunk to its position multiplies by alpha^(32 j c) for chunk index c,
 // digit by digit with constant tables (c = d0 + 8 d1 + 64 blk).
+// With four components (a 64-bit signature) the low word is the two-
+// component signature and the high word holds components 3 and 4, whose
+// groups are 4 symbols (x^12, x^16 per Horner step); their position factors
+// alpha^(96c) and alpha^(128c) are products of the component 1 and 2 tables,
+// so no further tables are needed.
 #pragma once
 
 #include "asj_internal.h"
@@ -63,8 +68,8 @@ __device__ __forceinline__ uint32_t fold_group(const uint32_t *w)
     }
 }
 
-// GF(2^16): both components of one 64-byte chunk, positions relative to the
-// chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
+// GF(2^16): components 1 and 2 of one 64-byte chunk, positions relative to
+// the chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
 template <int NSYM>
 __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
 {
@@ -78,7 +83,7 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
         const uint32_t t1 = (a1 << 16) ^ u;
         a1 = (t1 & 0xFFFFu) ^ asj_cmul16(t1 >> 16, red);
     }
-    if (NSYM == 2) {
+    if (NSYM >= 2) {
         // component 2: four groups of 8 symbols; p_v shifted by 2v stays below 2^30
 #pragma unroll
         for (int q = 3; q >= 0; q--) {
@@ -91,15 +96,47 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
     const int d0 = c & 7, d1 = (c >> 3) & 7;
     a1 = asj_cmul16(a1, tab + asj_tab_d0(1, d0) * ASJ_TAB_WORDS);
     a1 = asj_cmul16(a1, tab + asj_tab_d1(1, d1) * ASJ_TAB_WORDS);
-    if (NSYM == 2) {
+    if (NSYM >= 2) {
         a2 = asj_cmul16(a2, tab + asj_tab_d0(2, d0) * ASJ_TAB_WORDS);
         a2 = asj_cmul16(a2, tab + asj_tab_d1(2, d1) * ASJ_TAB_WORDS);
     }
     for (int blk = c >> 6; blk > 0; blk--) {
         a1 = asj_cmul16(a1, tab + asj_tab_blk(1) * ASJ_TAB_WORDS);
-        if (NSYM == 2) a2 = asj_cmul16(a2, tab + asj_tab_blk(2) * ASJ_TAB_WORDS);
+        if (NSYM >= 2) a2 = asj_cmul16(a2, tab + asj_tab_blk(2) * ASJ_TAB_WORDS);
     }
     return a1 | (a2 << 16);
+}
+
+// Multiplication by alpha^(32 j c) for j = 1, 2 (the position factors of
+// components 1 and 2); components 3 and 4 apply them in combination.
+template <int J>
+__device__ __forceinline__ uint32_t scale16(uint32_t v, const uint16_t *__restrict__ tab, int c)
+{
+    v = asj_cmul16(v, tab + asj_tab_d0(J, c & 7) * ASJ_TAB_WORDS);
+    v = asj_cmul16(v, tab + asj_tab_d1(J, (c >> 3) & 7) * ASJ_TAB_WORDS);
+    for (int blk = c >> 6; blk > 0; blk--) v = asj_cmul16(v, tab + asj_tab_blk(J) * ASJ_TAB_WORDS);
+    return v;
+}
+
+// GF(2^16): components 3 and 4 of one 64-byte chunk; returns s3 | s4 << 16.
+__device__ __forceinline__ uint32_t chunk_sig16_hi(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
+{
+    const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
+    uint32_t a3 = 0, a4 = 0;
+    // eight groups of 4 symbols (2 words): p_v shifted by 3v (below 2^25)
+    // plus the accumulator times x^12, and p_v shifted by 4v (below 2^28)
+    // plus the accumulator times x^16
+#pragma unroll
+    for (int q = 7; q >= 0; q--) {
+        const uint32_t t3 = (a3 << 12) ^ fold_group<1, 6, 3>(kd + 2 * q);
+        a3 = (t3 & 0xFFFFu) ^ asj_cmul16(t3 >> 16, red);
+        const uint32_t t4 = (a4 << 16) ^ fold_group<1, 8, 4>(kd + 2 * q);
+        a4 = (t4 & 0xFFFFu) ^ asj_cmul16(t4 >> 16, red);
+    }
+    // positions: alpha^(96c) = alpha^(32c) alpha^(64c), alpha^(128c) = (alpha^(64c))^2
+    a3 = scale16<2>(scale16<1>(a3, tab, c), tab, c);
+    a4 = scale16<2>(scale16<2>(a4, tab, c), tab, c);
+    return a3 | (a4 << 16);
 }
 
 // GF(2^8): byte symbols, NSYM components of 8 bits; component j of the chunk
@@ -177,12 +214,15 @@ __device__ __forceinline__ void load_tables(uint16_t *tab, const uint16_t *__res
 
 // Signature (or finalized plain hash) of each lane's key for a window of 64
 // keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes without
-// a key).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays.
+// a key).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
+// four GF(2^16) components wacc2 (64 entries) accumulates the high word,
+// returned in hi.
 template <int MODE, int NSYM>
 __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len,
                                                 int64_t *wst, int32_t *wex, uint32_t *wacc,
-                                                const uint16_t *tab)
+                                                const uint16_t *tab, uint32_t *wacc2, uint32_t &hi)
 {
+    constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
     const int lane = threadIdx.x % ASJ_WAVE;
     const int nfull = len / ASJ_CHUNK;
     const int incl = asj_wave_incl_scan(nfull);
@@ -190,6 +230,7 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
     wst[lane] = s;
     wex[lane] = incl - nfull;
     wacc[lane] = 0;
+    if (kHi) wacc2[lane] = 0;
     asj_wave_sync();
     // full chunks of all 64 keys, 64 per pass, one per lane: uniform code
     for (int base = 0; base < total; base += ASJ_WAVE) {
@@ -200,18 +241,21 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
             uint32_t kd[16];
             asj_load_full(data, wst[i] + (int64_t)c * ASJ_CHUNK, kd);
             atomicXor(&wacc[i], chunk_value<MODE, NSYM>(kd, tab, c));
+            if (kHi) atomicXor(&wacc2[i], chunk_sig16_hi(kd, tab, c));
         }
     }
     // tail pass: lane i takes key i's last, partial chunk
-    uint32_t v = 0;
+    uint32_t v = 0, vh = 0;
     const int rem = len - nfull * ASJ_CHUNK;
     if (rem > 0) {
         uint32_t kd[16];
         asj_load_tail(data, s + (int64_t)nfull * ASJ_CHUNK, rem, kd);
         v = chunk_value<MODE, NSYM>(kd, tab, nfull);
+        if (kHi) vh = chunk_sig16_hi(kd, tab, nfull);
     }
     asj_wave_sync();
     v ^= wacc[lane];
+    if (kHi) hi = vh ^ wacc2[lane];
     asj_wave_sync();
     if (MODE == ASJ_MODE_PLAIN) v = asj_mix32(v ^ ((uint32_t)len * 0xC2B2AE3Du));
     return v;

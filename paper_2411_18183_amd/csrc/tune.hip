@@ -91,6 +91,7 @@ std::vector<asj_opts> grid(const asj_opts &base, int64_t n_build, bool batch)
         }
         for (int kpw : kKeysPerWindow)
             for (uint32_t sched : {ASJ_PROBE_FUSED, ASJ_PROBE_SPLIT}) {
+                if (sched == ASJ_PROBE_SPLIT && base.sig.f == 16 && base.sig.nsym == 4) continue; // fused only
                 asj_opts o = base;
                 o.load_factor = lf;
                 o.keys_per_window = kpw;

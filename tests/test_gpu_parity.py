@@ -22,8 +22,10 @@ def A():
 
 def gpu_sigs(A, rel, f=16, nsym=2):
     keys = A.DeviceKeys.from_host(rel)
-    out = A.asj_signature(keys, f, nsym)
-    return out.cpu().numpy().view(np.uint32).astype(np.uint64)
+    out = A.asj_signature(keys, f, nsym).cpu().numpy()
+    if f * nsym == 64:  # two words per key, the low word first
+        return out.view(np.uint64)
+    return out.view(np.uint32).astype(np.uint64)
 
 
 SCHEDULES = ["split", "fused"]
@@ -59,7 +61,7 @@ def adversarial_keys(rng):
 
 
 @pytest.mark.parametrize("shift", [0, 1, 2, 3, 5, 15, 16])
-@pytest.mark.parametrize("params", [(16, 2), (16, 1), (8, 4), (8, 2)])
+@pytest.mark.parametrize("params", [(16, 2), (16, 1), (8, 4), (8, 2), (16, 4)])
 def test_signature_bitexact_adversarial(A, oracle, wl, shift, params):
     rng = np.random.default_rng(100 + shift)
     rel = wl.unaligned_copy(wl.from_keys(adversarial_keys(rng)), shift)
@@ -72,6 +74,7 @@ def test_signature_bitexact_workloads(A, oracle, wl, name, scale):
     w = getattr(wl, name)(scale=scale)
     for rel in (w.R, w.S):
         assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
+    assert np.array_equal(gpu_sigs(A, w.S, 16, 4), oracle.signatures(w.S, 16, 4))
 
 
 def test_signature_bitexact_batch_keys(A, oracle, wl):
@@ -160,6 +163,73 @@ def test_variant_signature_joins(A, oracle, wl, sched):
         assert ncand == want_cand
 
 
+def test_sig64_joins_equal_oracle(A, oracle, wl):
+    """64-bit signatures (f = 16, n = 4; fused schedule): exact pairs, exact
+    candidate counts (pairs of equal 64-bit signature), and the paper-literal
+    output on signature equality."""
+    for seed in range(4):
+        w = wl.random_small(seed, m=300 + 50 * seed, n=700, max_len=[2, 9, 70, 300][seed], alphabet=b"ab\x00")
+        want, want_cand = oracle.join_signature(w.R, w.S, f=16, nsym=4)
+        got, total, ncand = gpu_join(A, w.R, w.S, f=16, nsym=4)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), seed
+        assert ncand == want_cand, seed
+        lit, lit_cand = oracle.join_signature(w.R, w.S, f=16, nsym=4, verify=False)
+        got, total, ncand = gpu_join(A, w.R, w.S, f=16, nsym=4, flags=A.ASJ_NO_VERIFY)
+        assert np.array_equal(oracle.sort_pairs(got), lit) and ncand == lit_cand, seed
+        for kind, flag in (("semi", A.ASJ_SEMI), ("anti", A.ASJ_ANTI)):
+            got, _, _ = gpu_join(A, w.R, w.S, f=16, nsym=4, flags=flag)
+            assert np.array_equal(oracle.sort_pairs(got), oracle.join_variant(w.R, w.S, kind)), (seed, kind)
+    t = wl.tiny(scale=0.5)
+    got, total, ncand = gpu_join(A, t.R, t.S, f=16, nsym=4)
+    assert np.array_equal(oracle.sort_pairs(got), oracle.join_hash(t.R, t.S)) and ncand == total
+
+
+def test_sig64_separates_two_component_collisions(A, oracle, wl):
+    """Keys that differ by a three-symbol Reed-Solomon codeword of the
+    two-component code (its generator vanishes at alpha and alpha^2) share
+    the {16, 2} signature but not the {16, 4} one: the paper-literal join
+    matches them with two components and not with four."""
+    import random
+    rng = random.Random(5)
+    g0, g1 = oracle.gf_exp(16, 3), oracle.gf_exp(16, 1) ^ oracle.gf_exp(16, 2)  # (y + a)(y + a^2), g2 = 1
+    base = [rng.randrange(1, 65536) for _ in range(200)]
+    key = lambda sy: b"".join(int(v).to_bytes(2, "little") for v in sy)
+    variants = []
+    for i in (0, 31, 32, 77, 150, 197):  # inside a chunk, across chunk boundaries, at the end
+        t = rng.randrange(1, 65536)
+        k = list(base)
+        k[i] ^= oracle.mul_table(16, g0, t)
+        k[i + 1] ^= oracle.mul_table(16, g1, t)
+        k[i + 2] ^= t
+        variants.append(key(k))
+    R, S = wl.from_keys([key(base)]), wl.from_keys([key(base)] + variants)
+    s2 = oracle.signatures(S, 16, 2)
+    assert (s2 == s2[0]).all() and len(set(oracle.signatures(S, 16, 4).tolist())) == len(variants) + 1
+    got, total, ncand = gpu_join(A, R, S, flags=A.ASJ_NO_VERIFY)
+    assert total == ncand == len(variants) + 1
+    got, total, ncand = gpu_join(A, R, S, flags=A.ASJ_NO_VERIFY, f=16, nsym=4)
+    assert total == ncand == 1 and got.tolist() == [[0, 0]]
+    assert np.array_equal(gpu_sigs(A, S, 16, 4), oracle.signatures(S, 16, 4))
+
+
+def test_sig64_unsupported_forms(A, wl):
+    import torch
+    w = wl.random_small(1, m=20, n=20)
+    with pytest.raises(A.AsjError) as ei:
+        gpu_join(A, w.R, w.S, sched="split", f=16, nsym=4)
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+    b = wl.batch(scale=0.001, njoins=2)
+    R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
+    with pytest.raises(A.AsjError) as ei:
+        A.join_batch(R, S, b.r_seg, b.s_seg, f=16, nsym=4)
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+    out = torch.empty((64, 2), dtype=torch.int32)
+    with pytest.raises(A.AsjError) as ei:
+        A.asj_join_host(A.HostKeys.from_host(w.R, pin=False), A.HostKeys.from_host(w.S, pin=False), out,
+                        f=16, nsym=4)
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("sched", SCHEDULES)
 def test_duplicate_keys_multimap(A, oracle, wl, sched):
     keys_r = [b"k" * 100] * 150 + [b"x" * 7] * 3 + [b""] * 4 + [bytes([i % 7]) * (i % 300) for i in range(500)]
@@ -226,7 +296,10 @@ def test_rejects_bad_parameters(A, wl):
         A.asj_signature(rel, 8, 3)  # valid width, no kernel for it
     assert e.value.code == A.ASJ_EUNSUPPORTED
     with pytest.raises(A.AsjError) as e:
-        A.asj_signature(rel, 16, 3)  # 48 bits do not fit the 32-bit signature word
+        A.asj_signature(rel, 16, 3)  # 48 bits: valid, no kernel for it
+    assert e.value.code == A.ASJ_EUNSUPPORTED
+    with pytest.raises(A.AsjError) as e:
+        A.asj_signature(rel, 16, 5)  # 80 bits do not fit the 64-bit signature word
     assert e.value.code == A.ASJ_EINVAL
     with pytest.raises(A.AsjError) as e:
         A.asj_signature(rel, 12, 2)
