@@ -73,6 +73,7 @@ def parse():
                     help="also time signature vs plain joins on keys of one length, 4 B .. 4 KB")
     ap.add_argument("--host-budget", type=int, default=1 << 30, metavar="BYTES",
                     help="device budget of the partitioned host-memory join (0: skip the host-memory joins)")
+    ap.add_argument("--no-variants", action="store_true", help="skip the signature-width comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -120,6 +121,29 @@ def run_steps(A, torch, Rk, Sk, out, counts, steps, flags=0):
     for name, ms in recs:
         per.setdefault(name, []).append(ms)
     return (t1 - t0) * 1e3 / steps, {k: sum(v) / len(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
+
+
+def bench_signature_variants(A, torch, Rk, Sk, out, counts, n_pairs: int, steps: int, lf: float):
+    """Whole-join time and false candidates (signature-equal pairs whose keys
+    differ) for every signature width on the same inputs and table load
+    factor, verified and paper-literal."""
+    res = []
+    for f, nsym in ((16, 2), (16, 1), (8, 2), (8, 4), (16, 4)):
+        for verify in (True, False):
+            flags = 0 if verify else A.ASJ_NO_VERIFY
+            kw = dict(f=f, nsym=nsym, load_factor=lf, keys_per_window=64, flags=flags | A.ASJ_PROBE_FUSED)
+            A.asj_join(Rk, Sk, out, counts, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                A.asj_join(Rk, Sk, out, counts, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / steps
+            total, cand = (int(x) for x in counts.tolist())
+            res.append({"f": f, "nsym": nsym, "bits": f * nsym, "verify": verify, "ms": round(ms, 4),
+                        "pairs": total, "candidates": cand, "false_candidates": cand - n_pairs})
+            log(f"signature variant: {res[-1]}")
+    return res
 
 
 def tiny_instances(W, count: int, seed0: int = 1):
@@ -564,6 +588,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy kernel over {nb} bytes done")
 
+    variants = None
+    if not args.no_variants:
+        variants = bench_signature_variants(A, torch, Rk, Sk, out, counts, n_pairs, max(3, args.steps // 4), lf)
     host = None
     if args.host_budget > 0:
         host = bench_host(A, torch, w, expected, args.host_budget, Sk)
@@ -656,6 +683,7 @@ def main():
         "tiny_batched": tiny_batch,
         "tiny_single_join_latency": tiny_single,
         "host_memory_join": host,
+        "signature_variants": variants,
         "served": served,
         "autotune": tune,
         "length_sweep": sweep,
