@@ -304,7 +304,8 @@ def bench_tiny_latency(A, torch, W, runs: int = 1000):
 
 def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096),
                        probe_bytes: int = 1 << 29):
-    """Signature join vs plain byte-compare hash join on keys of one length
+    """Signature join vs plain byte-compare hash join (and the fingerprint
+    control: the plain join's key hash stored and compared) on keys of one length
     (R = |S| / 4, 20% of S copies R rows, bytes uniform over all 256 values;
     |S| = min(4M, probe_bytes / length)), both with the same fixed options
     (load factor 0.5, 64 keys per window, fused schedule)."""
@@ -315,7 +316,7 @@ def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 
         Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
         out = torch.empty((n + n // 4, 2), dtype=torch.int32, device="cuda")
         res = {"key_len": L, "R": w.R.n, "S": n}
-        for name, flags in (("signature", 0), ("plain", A.ASJ_PLAIN)):
+        for name, flags in (("signature", 0), ("plain", A.ASJ_PLAIN), ("fingerprint", A.ASJ_FINGERPRINT)):
             cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
             fl = flags | A.ASJ_PROBE_FUSED
             run = lambda: A.asj_join(Rk, Sk, out, cnt, load_factor=0.5, keys_per_window=64, flags=fl)
@@ -327,7 +328,7 @@ def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 
             torch.cuda.synchronize()
             res[f"ms_{name}"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
             res[f"pairs_{name}"] = int(cnt[0])
-        assert res["pairs_signature"] == res["pairs_plain"], res
+        assert res["pairs_signature"] == res["pairs_plain"] == res["pairs_fingerprint"], res
         res["signature_join_speedup"] = round(res["ms_plain"] / res["ms_signature"], 3)
         log(f"length sweep: {res}")
         rows.append(res)
@@ -578,6 +579,18 @@ def main():
                  "phases_ms": {k: round(v, 4) for k, v in plain_phase.items()},
                  "signature_join_speedup": round(ms_plain / ms_step, 3), "autotune": tune_plain}
         log(f"plain hash join: {ms_plain:.3f} ms/step")
+        # control: the same key hash kept in the table as a 32-bit fingerprint
+        # (isolates what the algebraic signature adds over any stored fingerprint)
+        tune_fp = None if args.no_autotune else A.autotune(Rk, Sk, out, counts_p, flags=A.ASJ_FINGERPRINT)
+        for _ in range(max(1, args.warmup)):
+            A.asj_join(Rk, Sk, out, counts_p, flags=A.ASJ_FINGERPRINT)
+        ms_fp, fp_phase, _ = run_steps(A, torch, Rk, Sk, out, counts_p, args.steps, flags=A.ASJ_FINGERPRINT)
+        assert int(counts_p[0]) == n_pairs, "fingerprint hash join disagrees on |T|"
+        plain["fingerprint_control"] = {
+            "ms_per_step": round(ms_fp, 4), "value": round(w.S.n / (ms_fp * 1e-3), 1), "candidates": int(counts_p[1]),
+            "phases_ms": {k: round(v, 4) for k, v in fp_phase.items()},
+            "signature_join_speedup": round(ms_fp / ms_step, 3), "autotune": tune_fp}
+        log(f"fingerprint control: {ms_fp:.3f} ms/step")
 
     if args.calibrate_copy > 0:
         nb = int(args.calibrate_copy)

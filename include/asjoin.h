@@ -56,6 +56,13 @@ extern "C" {
 #define ASJ_PLAIN 0x2u     /* baseline simple hash join (Section 2): a full-key multiplicative
                               hash instead of the signature; every occupied slot on the probe
                               path is compared by length and bytes (no stored fingerprint) */
+#define ASJ_FINGERPRINT 0x200u /* control for the baseline: the same full-key multiplicative hash
+                                as ASJ_PLAIN, but stored in the table as a 32-bit fingerprint and
+                                compared like a signature before any key byte -- it isolates what
+                                the algebraic signature adds over a non-algebraic fingerprint.
+                                Single joins (asj_build / asj_probe / asj_join) only; with
+                                ASJ_PLAIN or ASJ_NO_VERIFY: ASJ_EINVAL; asj_join_batch,
+                                asj_join_host and the server: ASJ_EUNSUPPORTED. */
 #define ASJ_PROBE_FUSED 0x4u /* probe schedule: each probe key is signed inside the probe kernel,
                                 right before its table walk and verification */
 #define ASJ_SORTED 0x10u      /* asj_join / asj_probe: the stored pairs (the first min(|T|, out_cap))

@@ -178,7 +178,9 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     if (opts) o = *opts;
     const int plain = (o.flags & ASJ_PLAIN) != 0;
     const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    const int fp = (o.flags & ASJ_FINGERPRINT) != 0;
     if (plain && !verify) return ASJ_EINVAL; // the plain table has no signature to trust
+    if (fp && (plain || !verify)) return ASJ_EINVAL;
     if (join_kind(o.flags) < 0) return ASJ_EINVAL;
     asj_sig_params sig = {16, 2};
     if (!plain) {
@@ -188,7 +190,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     float lf;
     int kpw, split;
     if (resolve_auto(0, r->n, o, &lf, &kpw, &split) != ASJ_OK) return ASJ_EINVAL;
-    const bool wide = !plain && sig64(sig);
+    const bool wide = !plain && !fp && sig64(sig);
     if (wide) { // 64-bit signatures: the fused probe schedule only
         if (o.flags & ASJ_PROBE_SPLIT) return ASJ_EUNSUPPORTED;
         split = 0;
@@ -205,6 +207,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->r = *r;
     t->capacity = cap;
     t->plain = plain;
+    t->fp = fp;
     t->verify = verify;
     t->sig = sig;
     t->keys_per_window = kpw;
@@ -236,8 +239,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         if (le == hipSuccess && t->validate) le = asj_launch_validate(r->offsets, r->n, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
-        tim_begin(plain ? "hash_build" : "sign_build", st);
-        le = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi);
+        tim_begin(plain ? "hash_build" : fp ? "fp_build" : "sign_build", st);
+        le = launch_sign_for(r, sig, plain || fp, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
@@ -306,7 +309,8 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     a.plain = t->plain;
     a.verify = t->verify;
     a.kind = t->kind;
-    const int mode = t->plain ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+    const int mode = (t->plain || t->fp) ? ASJ_MODE_PLAIN : (t->sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+    const int nsym = (t->plain || t->fp) ? 1 : t->sig.nsym;
     int32_t *pstatus = nullptr; // validation result of the probe relation
     if (t->validate && s->n > 0) {
         e = alloc_async(&pstatus, 1, st);
@@ -320,20 +324,20 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     }
     uint32_t *ssig = nullptr;
     if (!t->split || s->n == 0) {
-        tim_begin(t->plain ? "hash_probe_verify" : "sign_probe_verify", st);
-        e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        tim_begin(t->plain ? "hash_probe_verify" : t->fp ? "fp_probe_verify" : "sign_probe_verify", st);
+        e = asj_launch_probe(&a, mode, nsym, g_dev[dev].tab, kProbeGridCap, st);
         tim_end(st);
     } else {
         e = alloc_async(&ssig, (size_t)s->n, st);
         if (e == hipSuccess) {
-            tim_begin(t->plain ? "hash_S" : "sign_S", st);
-            e = launch_sign_for(s, t->sig, t->plain, ssig, g_dev[dev].tab, st, pstatus);
+            tim_begin(t->plain ? "hash_S" : t->fp ? "fp_S" : "sign_S", st);
+            e = launch_sign_for(s, t->sig, t->plain || t->fp, ssig, g_dev[dev].tab, st, pstatus);
             tim_end(st);
         }
         if (e == hipSuccess) {
             a.ssig = ssig;
             tim_begin(t->plain ? "hash_probe_verify" : "probe_verify", st);
-            e = asj_launch_probe(&a, mode, t->sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+            e = asj_launch_probe(&a, mode, nsym, g_dev[dev].tab, kProbeGridCap, st);
             tim_end(st);
         }
         if (ssig) (void)hipFreeAsync(ssig, st);
@@ -399,7 +403,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     *plain = (o.flags & ASJ_PLAIN) != 0;
     *verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (*plain && !*verify) return ASJ_EINVAL;
-    if (o.flags & ASJ_SORTED) return ASJ_EUNSUPPORTED;
+    if (o.flags & (ASJ_SORTED | ASJ_FINGERPRINT)) return ASJ_EUNSUPPORTED;
     if (validate) *validate = (o.flags & ASJ_VALIDATE) != 0;
     const int k = join_kind(o.flags);
     if (k < 0) return ASJ_EINVAL;
@@ -422,6 +426,7 @@ int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r)
     r->plain = (o.flags & ASJ_PLAIN) != 0;
     r->verify = (o.flags & ASJ_NO_VERIFY) == 0;
     if (r->plain && !r->verify) return ASJ_EINVAL;
+    if (o.flags & ASJ_FINGERPRINT) return ASJ_EUNSUPPORTED; // single joins only
     r->kind = join_kind(o.flags);
     if (r->kind < 0) return ASJ_EINVAL;
     r->sig = asj_sig_params{16, 2};

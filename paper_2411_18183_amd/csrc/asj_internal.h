@@ -173,6 +173,7 @@ struct asj_table {
     int64_t capacity;    // power of two
     int32_t *status;     // device word: 0 or ASJ_ETABLEFULL
     int plain;           // baseline table (no signature stored)
+    int fp;              // fingerprint control: the baseline's key hash stored and compared as a signature
     int verify;          // probe compares key bytes of candidates
     asj_sig_params sig;  // signature parameters of the build
     uint32_t *sig_hi;    // four GF(2^16) components: the build rows' high words (the slots hold the low words)

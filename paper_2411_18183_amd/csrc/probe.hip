@@ -409,6 +409,7 @@ hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, cons
                          : launch<ASJ_MODE_SIG16, 2, 0, 0, 1>(a, tab, grid_cap, st);
     }
     if (a->plain) return launch<ASJ_MODE_PLAIN, 1, 1, 1, 0>(a, tab, grid_cap, st);
+    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1, 0, 1, 0>(a, tab, grid_cap, st); // fingerprint
     if (mode == ASJ_MODE_SIG16 && nsym == 2) return launch_sig<ASJ_MODE_SIG16, 2>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch_sig<ASJ_MODE_SIG16, 1>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch_sig<ASJ_MODE_SIG8, 4>(a, tab, grid_cap, st);

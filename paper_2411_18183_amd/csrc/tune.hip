@@ -37,7 +37,7 @@ Key make_key(int batch, int64_t n_build, const asj_opts &o)
     (void)hipGetDevice(&k.dev);
     k.batch = batch;
     k.bucket = log2_bucket(n_build);
-    k.plain = (o.flags & ASJ_PLAIN) != 0;
+    k.plain = (o.flags & ASJ_PLAIN) ? 1 : (o.flags & ASJ_FINGERPRINT) ? 2 : 0;
     k.verify = (o.flags & ASJ_NO_VERIFY) == 0;
     k.f = k.plain ? 0 : (o.sig.f ? o.sig.f : 16);
     k.nsym = k.plain ? 0 : (o.sig.nsym ? o.sig.nsym : 2);

@@ -163,6 +163,30 @@ def test_variant_signature_joins(A, oracle, wl, sched):
         assert ncand == want_cand
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_fingerprint_control_equals_oracle(A, oracle, wl, sched):
+    """The baseline's key hash stored as a fingerprint: the same exact join;
+    its candidates (fingerprint-equal pairs) include every output pair."""
+    cases = [wl.random_small(seed, m=300, n=500, max_len=[2, 9, 80, 700][seed], alphabet=b"ab\x00")
+             for seed in range(4)]
+    cases.append(wl.tiny(scale=0.5))
+    cases.append(wl.large(scale=0.002))
+    for i, w in enumerate(cases):
+        want = oracle.join_hash(w.R, w.S)
+        got, total, ncand = gpu_join(A, w.R, w.S, sched=sched, flags=A.ASJ_FINGERPRINT)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), i
+        assert ncand >= total, i
+    for bad in (A.ASJ_FINGERPRINT | A.ASJ_PLAIN, A.ASJ_FINGERPRINT | A.ASJ_NO_VERIFY):
+        with pytest.raises(A.AsjError) as ei:
+            gpu_join(A, cases[0].R, cases[0].S, flags=bad)
+        assert ei.value.code == A.ASJ_EINVAL
+    b = wl.batch(scale=0.001, njoins=2)
+    with pytest.raises(A.AsjError) as ei:
+        A.join_batch(A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S), b.r_seg, b.s_seg,
+                     flags=A.ASJ_FINGERPRINT)
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+
+
 def test_sig64_joins_equal_oracle(A, oracle, wl):
     """64-bit signatures (f = 16, n = 4; fused schedule): exact pairs, exact
     candidate counts (pairs of equal 64-bit signature), and the paper-literal
