@@ -49,7 +49,7 @@
 static uint32_t field_poly(int f) { return f == 16 ? 0x1100Bu : 0x11Du; }
 static uint32_t field_order(int f) { return (1u << f) - 1u; } /* |GF*| */
 
-/* Log/antilog tables (Section 3.1: "logarithms and antilogarithms tables").
+/* Log/antilog tables (Section 3.1 multiplies with logarithm and antilogarithm tables).
  * exp[e] = alpha^e for 0 <= e < 2^f - 1; log[exp[e]] = e.  log[0] unused. */
 static uint16_t exp16[65536], log16[65536];
 static uint16_t exp8[256], log8[256];
