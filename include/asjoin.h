@@ -130,18 +130,23 @@ typedef struct asj_sig_params {
 
 /* Join options.  sig = {0, 0} means {16, 2}; load_factor = table fill
  * bound (capacity = next power of two >= m / load_factor, at least 64);
- * keys_per_window = probe keys a wave takes at a time, 1..64.  Options left
- * to the library -- load_factor <= 0, keys_per_window <= 0, neither
+ * keys_per_window = probe keys a wave takes at a time, 1..64;
+ * grid_rounds = size of the probe kernel's grid in units of the blocks the
+ * device holds at once, 1..8 (waves then take every grid-th window: one
+ * round keeps every block resident for the whole launch, more rounds
+ * balance windows of uneven cost).  Options left to the library --
+ * load_factor <= 0, keys_per_window <= 0, grid_rounds <= 0, neither
  * ASJ_PROBE_FUSED nor ASJ_PROBE_SPLIT -- take the value asj_autotune (or
  * asj_autotune_batch for asj_join_batch) recorded on this device for the
  * same size class (build rows rounded up to a power of two, same signature
- * parameters and ASJ_PLAIN / ASJ_NO_VERIFY flags), else the defaults 0.5,
- * 64 and the fused schedule. */
+ * parameters and ASJ_PLAIN / ASJ_NO_VERIFY / ASJ_FINGERPRINT flags), else
+ * the defaults 0.5, 64, 2 rounds and the fused schedule. */
 typedef struct asj_opts {
     asj_sig_params sig;
     float load_factor;
     uint32_t flags;
     int32_t keys_per_window;
+    int32_t grid_rounds;
 } asj_opts;
 
 /* Opaque build-side hash table H_sign (Section 3.2): an open-addressing
@@ -322,16 +327,17 @@ int asj_join_host_release(void);
 typedef struct asj_tune_result {
     asj_opts best;    /* fastest options found (explicit values and schedule flag) */
     float best_ms;    /* median time of one whole call with `best` */
-    float default_ms; /* median time with the defaults (0.5, 64, fused) */
+    float default_ms; /* median time with the defaults (0.5, 64, 2 rounds, fused) */
     int32_t trials;   /* configurations timed besides the defaults */
 } asj_tune_result;
 
 /* Autotuner for asj_join: times whole joins of r and s (one untimed and
  * three timed calls per configuration, median, HIP events on `stream`) over
  * the load factors {0.25, 0.35, 0.5, 0.7} that give distinct capacities,
- * keys_per_window {16, 32, 64} and both probe schedules, with the signature
- * parameters and ASJ_PLAIN / ASJ_NO_VERIFY flags of `opts` (NULL = defaults;
- * its load factor, keys per window and schedule are ignored), and records the
+ * keys_per_window {16, 32, 64}, both probe schedules and grid_rounds
+ * {1, 2, 4}, with the signature parameters and ASJ_PLAIN / ASJ_NO_VERIFY /
+ * ASJ_FINGERPRINT flags of `opts` (NULL = defaults; its load factor, keys
+ * per window, grid rounds and schedule are ignored), and records the
  * fastest for later calls that leave these options to the library (see
  * asj_opts).  out, out_cap and out_count are the result buffers of the trial
  * joins (as for asj_join); `res` (may be NULL) receives the outcome.

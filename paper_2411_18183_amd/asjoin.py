@@ -54,7 +54,7 @@ class asj_sig_params(ctypes.Structure):
 
 class asj_opts(ctypes.Structure):
     _fields_ = [("sig", asj_sig_params), ("load_factor", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("keys_per_window", ctypes.c_int32)]
+                ("keys_per_window", ctypes.c_int32), ("grid_rounds", ctypes.c_int32)]
 
 
 class asj_batch(ctypes.Structure):
@@ -210,14 +210,14 @@ class Table:
             pass
 
 
-def _opts(f, nsym, load_factor, flags, keys_per_window=0) -> asj_opts:
-    return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags), int(keys_per_window))
+def _opts(f, nsym, load_factor, flags, keys_per_window=0, grid_rounds=0) -> asj_opts:
+    return asj_opts(asj_sig_params(f, nsym), float(load_factor), int(flags), int(keys_per_window), int(grid_rounds))
 
 
 def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.0, flags: int = 0,
-              keys_per_window: int = 0, stream=None) -> Table:
+              keys_per_window: int = 0, grid_rounds: int = 0, stream=None) -> Table:
     k = R.c()
-    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
     h = ctypes.c_void_p()
     _check(lib().asj_build(ctypes.byref(k), ctypes.byref(o), ctypes.byref(h), _stream(stream)), "asj_build")
     return Table(h, R)
@@ -233,10 +233,10 @@ def asj_probe(t: Table, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, 
 
 
 def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, f: int = 16, nsym: int = 2,
-             load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, stream=None):
+             load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, grid_rounds: int = 0, stream=None):
     """Launch a whole join.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
     kr, ks = R.c(), S.c()
-    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
     cap = out.shape[0]
     _check(lib().asj_join(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
                           ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.c_void_p(counts.data_ptr()),
@@ -292,14 +292,14 @@ class HostKeys:
 
 
 def asj_join_host(R: HostKeys, S: HostKeys, out: torch.Tensor, f: int = 16, nsym: int = 2,
-                  load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, hbm_budget: int = 0,
+                  load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, grid_rounds: int = 0, hbm_budget: int = 0,
                   partitions: int = 0, stream=None):
     """Join host-resident relations within a device-memory budget.  out: cpu int32 [cap, 2].
     Returns (|T|, stats dict); the first min(|T|, cap) rows of out hold pairs."""
     if out.is_cuda or out.dtype != torch.int32 or not out.is_contiguous():
         raise ValueError("out must be a contiguous cpu int32 tensor [cap, 2]")
     kr, ks = R.c(), S.c()
-    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
     ho = asj_host_opts(int(hbm_budget), int(partitions), 0)
     st = asj_host_stats()
     cnt = ctypes.c_int64(0)
@@ -351,8 +351,8 @@ def _ptr(t):
 
 
 def asj_batch_workspace_bytes(njoins: int, n_build: int, n_probe: int, f: int = 16, nsym: int = 2,
-                              load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0) -> int:
-    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+                              load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, grid_rounds: int = 0) -> int:
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
     v = lib().asj_batch_workspace_bytes(int(njoins), int(n_build), int(n_probe), ctypes.byref(o))
     if v < 0:
         raise AsjError(ASJ_EINVAL, "asj_batch_workspace_bytes")
@@ -362,7 +362,7 @@ def asj_batch_workspace_bytes(njoins: int, n_build: int, n_probe: int, f: int = 
 def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: torch.Tensor, out: torch.Tensor,
                    out_seg: torch.Tensor, out_count: torch.Tensor, cand_count: Optional[torch.Tensor] = None,
                    done_clock: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None, f: int = 16,
-                   nsym: int = 2, load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, stream=None):
+                   nsym: int = 2, load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0, grid_rounds: int = 0, stream=None):
     """Launch a batch of joins (see asj_batch in the header).  All tensors on the device:
     r_seg/s_seg/out_seg int64 [J+1], out int32 [*, 2], out_count (and cand_count) int64 [J],
     done_clock int64 [J+1] (device clock ticks), workspace uint8 (optional)."""
@@ -373,7 +373,7 @@ def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: tor
     b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count),
                   _ptr(cand_count), _ptr(done_clock), _ptr(workspace),
                   int(workspace.numel()) if workspace is not None else 0)
-    o = _opts(f, nsym, load_factor, flags, keys_per_window)
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
     _check(lib().asj_join_batch(ctypes.byref(b), ctypes.byref(o), _stream(stream)), "asj_join_batch")
 
 
@@ -381,14 +381,14 @@ def _tune_dict(r: asj_tune_result) -> dict:
     b = r.best
     sched = "split" if b.flags & ASJ_PROBE_SPLIT else "fused"
     return {"load_factor": round(float(b.load_factor), 4), "keys_per_window": int(b.keys_per_window),
-            "schedule": sched, "best_ms": round(float(r.best_ms), 4), "default_ms": round(float(r.default_ms), 4),
+            "grid_rounds": int(b.grid_rounds), "schedule": sched, "best_ms": round(float(r.best_ms), 4), "default_ms": round(float(r.default_ms), 4),
             "trials": int(r.trials)}
 
 
 def autotune(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, out_count: torch.Tensor, f: int = 16, nsym: int = 2,
              flags: int = 0, stream=None) -> dict:
     """Run the library's autotuner on these relations (see asj_autotune); later calls that leave the load
-    factor, keys per window and schedule at 0 use its choice."""
+    factor, keys per window, grid rounds and schedule at 0 use its choice."""
     rk, sk = R.c(), S.c()
     o = _opts(f, nsym, 0.0, flags)
     res = asj_tune_result()

@@ -135,7 +135,7 @@ int join_kind(uint32_t flags)
 // wins, then the autotuner's record for this size class, then the defaults
 // (0.5, 64, fused -- fused was faster on every measured workload).
 // ASJ_EINVAL for contradictory schedule flags or a load factor >= 1.
-int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *kpw, int *split)
+int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *kpw, int *split, int *rounds)
 {
     const bool fused = (o.flags & ASJ_PROBE_FUSED) != 0, sp = (o.flags & ASJ_PROBE_SPLIT) != 0;
     if (fused && sp) return ASJ_EINVAL;
@@ -147,6 +147,8 @@ int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *
                ? o.keys_per_window
                : (tuned ? t.keys_per_window : ASJ_DEFAULT_KEYS_PER_WINDOW);
     *split = fused ? 0 : sp ? 1 : (tuned ? t.split : 0);
+    *rounds = (o.grid_rounds >= 1 && o.grid_rounds <= 8) ? o.grid_rounds : (tuned ? t.grid_rounds : 2);
+    if (o.grid_rounds > 8) return ASJ_EINVAL;
     return ASJ_OK;
 }
 
@@ -188,8 +190,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         if (rc != ASJ_OK) return rc;
     }
     float lf;
-    int kpw, split;
-    if (resolve_auto(0, r->n, o, &lf, &kpw, &split) != ASJ_OK) return ASJ_EINVAL;
+    int kpw, split, rounds;
+    if (resolve_auto(0, r->n, o, &lf, &kpw, &split, &rounds) != ASJ_OK) return ASJ_EINVAL;
     const bool wide = !plain && !fp && sig64(sig);
     if (wide) { // 64-bit signatures: the fused probe schedule only
         if (o.flags & ASJ_PROBE_SPLIT) return ASJ_EUNSUPPORTED;
@@ -211,6 +213,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->verify = verify;
     t->sig = sig;
     t->keys_per_window = kpw;
+    t->grid_rounds = rounds;
     t->split = split;
     t->sorted = (o.flags & ASJ_SORTED) != 0;
     t->validate = (o.flags & ASJ_VALIDATE) != 0;
@@ -306,6 +309,7 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     a.out_count = out_count;
     a.cand_count = cand_count;
     a.table_status = t->status;
+    a.grid_rounds = t->grid_rounds;
     a.plain = t->plain;
     a.verify = t->verify;
     a.kind = t->kind;
@@ -396,8 +400,10 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
 }
 
 int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
-               int *kpw, int *split, int *validate = nullptr, int *kind = nullptr)
+               int *kpw, int *split, int *validate = nullptr, int *kind = nullptr, int *rounds_out = nullptr)
 {
+    int rounds_local = 2;
+    int *rounds = rounds_out ? rounds_out : &rounds_local;
     asj_opts o = {};
     if (opts) o = *opts;
     *plain = (o.flags & ASJ_PLAIN) != 0;
@@ -414,7 +420,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
         if (rc != ASJ_OK) return rc;
         if (sig64(*sig)) return ASJ_EUNSUPPORTED; // 64-bit signatures: single joins only
     }
-    return resolve_auto(1, n_build, o, lf, kpw, split);
+    return resolve_auto(1, n_build, o, lf, kpw, split, rounds);
 }
 
 } // namespace
@@ -435,7 +441,7 @@ int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r)
         if (rc != ASJ_OK) return rc;
         if (sig64(r->sig)) return ASJ_EUNSUPPORTED; // 64-bit signatures: asj_join / asj_probe only
     }
-    return resolve_auto(0, n_build, o, &r->lf, &r->kpw, &r->split);
+    return resolve_auto(0, n_build, o, &r->lf, &r->kpw, &r->split, &r->grid_rounds);
 }
 
 const uint16_t *asj_device_tables(int *dev)
@@ -586,7 +592,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     asj_sig_params sig;
     float lf;
     int validate, kind;
-    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind);
+    int rounds = 2;
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind, &rounds);
     if (rc != ASJ_OK) return rc;
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
@@ -659,6 +666,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.out_seg = b->out_seg;
         a.rows_done = rows_done;
         a.done_clock = b->done_clock;
+        a.grid_rounds = rounds;
         const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
         if (split && b->s.n > 0) {
             tim_begin(plain ? "hash_S" : "sign_S", st);

@@ -178,6 +178,7 @@ struct asj_table {
     asj_sig_params sig;  // signature parameters of the build
     uint32_t *sig_hi;    // four GF(2^16) components: the build rows' high words (the slots hold the low words)
     int keys_per_window; // probe keys per wave window used by probes of this table
+    int grid_rounds;     // probe grid in units of the blocks the device holds at once
     int split;           // probes sign the probe keys in a separate kernel first
     int sorted;          // probes sort their output pairs by (r_id, s_id)
     int validate;        // probes check the probe relation's offsets first
@@ -193,6 +194,7 @@ struct asj_tuned {
     float load_factor;
     int keys_per_window;
     int split;
+    int grid_rounds;
 };
 bool asj_tuned_lookup(int batch, int64_t n_build, const asj_opts &o, asj_tuned *t);
 void asj_tuned_store(int batch, int64_t n_build, const asj_opts &o, const asj_tuned &t);
@@ -203,7 +205,7 @@ void asj_tuned_store(int batch, int64_t n_build, const asj_opts &o, const asj_tu
 // build side of n_build rows.
 struct asj_resolved {
     asj_sig_params sig;
-    int plain, verify, kind, split, kpw;
+    int plain, verify, kind, split, kpw, grid_rounds;
     float lf;
 };
 int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r);
@@ -282,6 +284,7 @@ struct asj_probe_args {
     int plain;
     int verify;
     int keys_per_window; // probe keys per wave window (1..64)
+    int grid_rounds;     // > 0: grid = grid_rounds x the kernel's resident blocks (capped by grid_cap)
     int kind;            // ASJ_KIND_*: inner, semi, anti or left outer join of the probe relation
     // batch of joins (njoins > 0): probe row k belongs to join j with
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with

@@ -366,6 +366,21 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         atomicAdd((unsigned long long *)a.cand_count, (unsigned long long)wave_cand);
 }
 
+// Blocks of `kernel` that the device holds at once (blocks per compute unit
+// from the occupancy calculator x compute units); 0 when the runtime cannot
+// say.
+int64_t resident_blocks(const void *kernel, int block)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || cus <= 0 || per <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (int64_t)cus * per;
+}
+
 template <int MODE, int NSYM, int PLAIN, int VERIFY, int PRESIGNED>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
@@ -374,6 +389,14 @@ hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hi
     constexpr int kWaves = Shape<PRESIGNED>::waves;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
+    if (a->grid_rounds > 0) { // the grid in rounds of resident blocks
+        static const int64_t res_batch = resident_blocks(
+            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED>), kBlock);
+        static const int64_t res_single = resident_blocks(
+            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED>), kBlock);
+        const int64_t resident = a->njoins > 0 ? res_batch : res_single;
+        if (resident > 0 && blocks > resident * a->grid_rounds) blocks = resident * a->grid_rounds;
+    }
     if (blocks < 1) blocks = 1;
     if (a->njoins > 0)
         hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED>), dim3((unsigned)blocks),

@@ -234,6 +234,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         a.out_seg = (const int64_t *)(d + o_oseg);
         a.rows_done = (int64_t *)(d + o_done);
         a.done_clock = nullptr;
+        a.grid_rounds = S->tbl.grid_rounds;
         const int mode = S->tbl.plain ? ASJ_MODE_PLAIN : (S->tbl.sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
         if (S->tbl.split && K > 0) {
             const asj_keys keys = {a.sdata, a.soff, a.sids, K};

@@ -631,6 +631,7 @@ int enqueue_probe(Ctx &c, const Table &t, Slot &s, const Range &r)
         a.cap = s.out_cap;
         a.out_count = s.dcount;
         a.table_status = t.status;
+        a.grid_rounds = c.ro.grid_rounds;
         a.plain = c.ro.plain;
         a.verify = c.ro.verify;
         a.kind = c.ro.kind;

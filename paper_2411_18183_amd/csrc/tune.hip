@@ -1,5 +1,6 @@
 // Autotuner: times whole joins over a grid of table load factors, probe
-// keys per window and both probe schedules on the caller's relations, keeps
+// keys per window, both probe schedules and probe grid sizes (1, 2 or 4
+// rounds of resident blocks) on the caller's relations, keeps
 // the fastest, and records it per build-size class so that later calls that
 // leave these options at zero use it.
 #include <algorithm>
@@ -46,6 +47,7 @@ Key make_key(int batch, int64_t n_build, const asj_opts &o)
 
 constexpr float kLoadFactors[] = {0.25f, 0.35f, 0.5f, 0.7f};
 constexpr int kKeysPerWindow[] = {16, 32, 64};
+constexpr int kGridRounds[] = {1, 2, 4};
 constexpr int kReps = 3;
 
 int64_t capacity_for(int64_t n, float lf)
@@ -77,7 +79,7 @@ int time_runs(Run run, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms)
 
 // The grid: every load factor that gives a distinct table capacity for
 // n_build rows (all four for a batch, whose segments differ), every keys per
-// window, both schedules.
+// window, both schedules, every grid size.
 std::vector<asj_opts> grid(const asj_opts &base, int64_t n_build, bool batch)
 {
     std::vector<asj_opts> g;
@@ -90,14 +92,16 @@ std::vector<asj_opts> grid(const asj_opts &base, int64_t n_build, bool batch)
             caps.push_back(c);
         }
         for (int kpw : kKeysPerWindow)
-            for (uint32_t sched : {ASJ_PROBE_FUSED, ASJ_PROBE_SPLIT}) {
-                if (sched == ASJ_PROBE_SPLIT && base.sig.f == 16 && base.sig.nsym == 4) continue; // fused only
-                asj_opts o = base;
-                o.load_factor = lf;
-                o.keys_per_window = kpw;
-                o.flags = flags | sched;
-                g.push_back(o);
-            }
+            for (uint32_t sched : {ASJ_PROBE_FUSED, ASJ_PROBE_SPLIT})
+                for (int rounds : kGridRounds) {
+                    if (sched == ASJ_PROBE_SPLIT && base.sig.f == 16 && base.sig.nsym == 4) continue; // fused only
+                    asj_opts o = base;
+                    o.load_factor = lf;
+                    o.keys_per_window = kpw;
+                    o.grid_rounds = rounds;
+                    o.flags = flags | sched;
+                    g.push_back(o);
+                }
     }
     return g;
 }
@@ -114,6 +118,7 @@ int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, as
     asj_opts defaults = base;
     defaults.load_factor = 0.5f;
     defaults.keys_per_window = ASJ_DEFAULT_KEYS_PER_WINDOW;
+    defaults.grid_rounds = 2;
     defaults.flags = (base.flags & ~(ASJ_PROBE_FUSED | ASJ_PROBE_SPLIT)) | ASJ_PROBE_FUSED;
     float def_ms = 0.0f, best_ms = 0.0f;
     asj_opts best = defaults;
@@ -135,7 +140,7 @@ int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, as
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != ASJ_OK) return rc;
-    asj_tuned t = {best.load_factor, best.keys_per_window, (best.flags & ASJ_PROBE_SPLIT) ? 1 : 0};
+    asj_tuned t = {best.load_factor, best.keys_per_window, (best.flags & ASJ_PROBE_SPLIT) ? 1 : 0, best.grid_rounds};
     asj_tuned_store(batch ? 1 : 0, n_build, base, t);
     if (res) {
         res->best = best;
@@ -149,7 +154,7 @@ int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, as
 bool tunable(const asj_opts &o)
 {
     return !((o.flags & ASJ_PROBE_FUSED) && (o.flags & ASJ_PROBE_SPLIT)) && o.load_factor >= 0.0f &&
-           o.load_factor < 1.0f && o.keys_per_window <= ASJ_WAVE;
+           o.load_factor < 1.0f && o.keys_per_window <= ASJ_WAVE && o.grid_rounds <= 8;
 }
 
 } // namespace

@@ -71,7 +71,7 @@ class _Keys(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("f", ctypes.c_int32), ("nsym", ctypes.c_int32), ("load_factor", ctypes.c_float),
-                ("flags", ctypes.c_uint32), ("keys_per_window", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("keys_per_window", ctypes.c_int32), ("grid_rounds", ctypes.c_int32)]
 
 
 class _HostOpts(ctypes.Structure):
@@ -102,6 +102,6 @@ def test_host_join_checks_its_arguments_on_the_host(lib):
         ho = _HostOpts(budget, parts, 0)
         assert f(P(R), P(R), None, P(ho), out, ctypes.c_int64(4), P(cnt), None, None) == -1
     # sorted output is not offered for host joins
-    o = _Opts(16, 2, 0.0, 0x10, 0)
+    o = _Opts(16, 2, 0.0, 0x10, 0, 0)
     assert f(P(R), P(R), P(o), None, out, ctypes.c_int64(4), P(cnt), None, None) == -6
     assert cnt.value == -7  # never written on a rejected call

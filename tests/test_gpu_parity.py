@@ -334,6 +334,20 @@ def test_rejects_bad_parameters(A, wl):
         A.asj_build(rel, flags=A.ASJ_PLAIN | A.ASJ_NO_VERIFY)
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_grid_rounds_do_not_change_the_output(A, oracle, wl, sched):
+    """The probe grid (1 .. 8 rounds of resident blocks) only changes which
+    wave takes which window."""
+    w = wl.large(scale=0.004)
+    want = oracle.join_hash(w.R, w.S)
+    for rounds in (1, 2, 3, 8):
+        got, total, _ = gpu_join(A, w.R, w.S, sched=sched, grid_rounds=rounds)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), rounds
+    with pytest.raises(A.AsjError) as ei:
+        gpu_join(A, w.R, w.S, grid_rounds=9)
+    assert ei.value.code == A.ASJ_EINVAL
+
+
 def test_contradictory_schedule_flags_rejected(A, wl):
     w = wl.random_small(1, m=10, n=10)
     with pytest.raises(A.AsjError):
