@@ -44,8 +44,10 @@ void tim_begin(const char *name, hipStream_t st)
 {
     if (!g_tim.on || g_tim.count >= kMaxTimed) return;
     int i = g_tim.count;
+    // timing-only events: no system-scope fence (no cache writeback and
+    // invalidation between the kernels they bracket)
     for (int e = 0; e < 2; e++)
-        if (!g_tim.ev[2 * i + e]) (void)hipEventCreate(&g_tim.ev[2 * i + e]);
+        if (!g_tim.ev[2 * i + e]) (void)hipEventCreateWithFlags(&g_tim.ev[2 * i + e], hipEventDisableSystemFence);
     g_tim.names[i] = name;
     (void)hipEventRecord(g_tim.ev[2 * i], st);
 }
@@ -237,8 +239,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     do {
         hipError_t le;
         tim_begin("table_init", st);
-        le = asj_launch_fill64(t->slots, cap, ASJ_EMPTY_SLOT, st);
-        if (le == hipSuccess) le = asj_launch_fill_i32(t->status, 1, 0, st);
+        le = asj_launch_table_init(t->slots, cap, t->status, st);
         if (le == hipSuccess && t->validate) le = asj_launch_validate(r->offsets, r->n, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
@@ -288,8 +289,7 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
     int dev = 0;
     int rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
-    hipError_t e = asj_launch_fill_i64(out_count, 1, 0, st);
-    if (e == hipSuccess && cand_count) e = asj_launch_fill_i64(cand_count, 1, 0, st);
+    hipError_t e = asj_launch_zero2(out_count, cand_count, st);
     if (e != hipSuccess) return hip_fail(e);
     asj_probe_args a = {};
     a.rdata = t->r.data;

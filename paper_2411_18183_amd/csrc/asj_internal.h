@@ -236,6 +236,10 @@ hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, h
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+// slots[0 .. cap) = empty and *status = ASJ_OK in one launch.
+hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st);
+// *a = 0 and, when b is not NULL, *b = 0 in one launch.
+hipError_t asj_launch_zero2(int64_t *a, int64_t *b, hipStream_t st);
 hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
                              int32_t *status, hipStream_t st);
 

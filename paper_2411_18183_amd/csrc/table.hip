@@ -34,6 +34,21 @@ __global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v)
         p[i] = v;
 }
 
+// A new table: every slot empty and the status word cleared, in one launch.
+__global__ void table_init_kernel(uint64_t *__restrict__ slots, int64_t cap, int32_t *__restrict__ status)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) *status = ASJ_OK;
+    for (int64_t i = i0; i < cap; i += (int64_t)gridDim.x * blockDim.x) slots[i] = ASJ_EMPTY_SLOT;
+}
+
+// Two 64-bit counters cleared in one launch (b may be NULL).
+__global__ void zero2_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b)
+{
+    if (threadIdx.x == 0) *a = 0;
+    if (threadIdx.x == 1 && b) *b = 0;
+}
+
 __global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -93,6 +108,19 @@ hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill64_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st)
+{
+    hipLaunchKernelGGL(table_init_kernel, dim3(grid_for(cap > 0 ? cap : 1, 256, 16384)), dim3(256), 0, st, slots, cap,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_zero2(int64_t *a, int64_t *b, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, st, a, b);
     return hipGetLastError();
 }
 

@@ -110,7 +110,8 @@ template <class RunWith>
 int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, asj_tune_result *res, hipStream_t st)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         return ASJ_EHIP;
     }
