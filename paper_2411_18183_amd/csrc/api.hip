@@ -174,6 +174,8 @@ hipError_t alloc_async(T **p, size_t count, hipStream_t st)
     return hipMallocAsync((void **)p, sizeof(T) * count, st);
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t st)
 {
     if (!table_out || !keys_ok(r)) return ASJ_EINVAL;
@@ -222,19 +224,21 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->kind = join_kind(o.flags);
     t->stream = st;
     t->device = dev;
-    uint32_t *sig_r = nullptr;
-    hipError_t e = alloc_async(&t->slots, (size_t)cap, st);
-    if (e == hipSuccess) e = alloc_async(&t->status, 1, st);
-    if (e == hipSuccess) e = alloc_async(&sig_r, (size_t)r->n, st);
-    if (e == hipSuccess && wide) e = alloc_async(&t->sig_hi, (size_t)r->n, st);
+    // one stream-ordered allocation: slots | status | signatures (low, high words)
+    const size_t o_status = align256(8 * (size_t)cap);
+    const size_t o_sig = align256(o_status + 4);
+    const size_t o_hi = align256(o_sig + 4 * (size_t)(r->n > 0 ? r->n : 1));
+    const size_t bytes = wide ? align256(o_hi + 4 * (size_t)(r->n > 0 ? r->n : 1)) : o_hi;
+    hipError_t e = hipMallocAsync(&t->block, bytes, st);
     if (e != hipSuccess) {
-        if (t->slots) (void)hipFreeAsync(t->slots, st);
-        if (t->status) (void)hipFreeAsync(t->status, st);
-        if (sig_r) (void)hipFreeAsync(sig_r, st);
-        if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, st);
         free(t);
         return hip_fail(e);
     }
+    uint8_t *blk = (uint8_t *)t->block;
+    t->slots = (uint64_t *)blk;
+    t->status = (int32_t *)(blk + o_status);
+    uint32_t *sig_r = (uint32_t *)(blk + o_sig);
+    t->sig_hi = wide ? (uint32_t *)(blk + o_hi) : nullptr;
     int out_rc = ASJ_OK;
     do {
         hipError_t le;
@@ -252,11 +256,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
     } while (0);
-    (void)hipFreeAsync(sig_r, st);
     if (out_rc != ASJ_OK) {
-        (void)hipFreeAsync(t->slots, st);
-        (void)hipFreeAsync(t->status, st);
-        if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, st);
+        (void)hipFreeAsync(t->block, st);
         free(t);
         return out_rc;
     }
@@ -353,11 +354,9 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
 int table_free_impl(asj_table *t)
 {
     if (!t) return ASJ_OK;
-    hipError_t e1 = hipFreeAsync(t->slots, t->stream);
-    hipError_t e2 = hipFreeAsync(t->status, t->stream);
-    if (t->sig_hi) (void)hipFreeAsync(t->sig_hi, t->stream);
+    const hipError_t e = hipFreeAsync(t->block, t->stream);
     free(t);
-    return (e1 == hipSuccess && e2 == hipSuccess) ? ASJ_OK : ASJ_EHIP;
+    return e == hipSuccess ? ASJ_OK : ASJ_EHIP;
 }
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
@@ -365,8 +364,6 @@ struct BatchLayout {
     size_t desc, rows_done, tot, status, win_r, win_s, sig, ssig, slots, bytes;
     int64_t slot_bound, win_r_cap, win_s_cap;
 };
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf, BatchLayout *L)
 {

@@ -169,6 +169,7 @@ __device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)
 // The build-side table (asj_table in the public header).
 struct asj_table {
     asj_keys r;          // borrowed build relation
+    void *block;         // one device allocation holding slots, status and the build signatures
     uint64_t *slots;     // capacity slots
     int64_t capacity;    // power of two
     int32_t *status;     // device word: 0 or ASJ_ETABLEFULL
