@@ -152,6 +152,26 @@ __device__ __forceinline__ void asj_load_tail(const uint8_t *__restrict__ data, 
     }
 }
 
+// Tail chunk read as a full chunk when the 68 bytes from the 4-byte-aligned
+// address below a all lie before `end` (the end of the relation's keys, whose
+// bytes run back to back, so the words past this key hold the next keys'
+// bytes): 4 wide loads instead of up to 17 guarded ones; bytes at or past
+// rem are masked to zero.  Near the end of the keys, the guarded loader.
+__device__ __forceinline__ void asj_load_tail_fast(const uint8_t *__restrict__ data, int64_t a, int rem, int64_t end,
+                                                   uint32_t kd[16])
+{
+    if ((a & ~(int64_t)3) + 68 <= end) {
+        asj_load_full(data, a, kd);
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+            const int nb = rem - 4 * t;
+            kd[t] &= nb >= 4 ? 0xFFFFFFFFu : (nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u));
+        }
+    } else {
+        asj_load_tail(data, a, rem, kd);
+    }
+}
+
 // Largest i in [0, 64) with ex[i] <= x, for a non-decreasing ex[] in LDS
 // whose first entry is 0.
 __device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)

@@ -172,6 +172,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
     };
 
     const bool pairs_out = a.kind == ASJ_KIND_INNER || a.kind == ASJ_KIND_LEFT; // the matching pairs themselves
+    const int64_t send = (PRESIGNED || a.n <= 0) ? 0 : a.soff[a.n]; // the probe keys' bytes end here
     const int kpw = a.keys_per_window;
     const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
     const int64_t stride = (int64_t)gridDim.x * kWaves;
@@ -236,7 +237,8 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];
         } else {
-            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, wst, wex, wacc, tab, kacc2[kHi ? wave : 0], sg_hi);
+            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, send, wst, wex, wacc, tab, kacc2[kHi ? wave : 0],
+                                              sg_hi);
         }
 
         Walk wk;

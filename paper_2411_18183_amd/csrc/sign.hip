@@ -31,6 +31,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
     const int64_t nwin = (n + ASJ_WAVE - 1) / ASJ_WAVE;
+    const int64_t end = off[n]; // the keys' bytes end here
     for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
         const int64_t k = w * ASJ_WAVE + lane;
         int64_t s = 0;
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
             len = (int)(off[k + 1] - s);
         }
         uint32_t hi = 0;
-        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, kst[wave], kex[wave], kacc[wave], tab,
+        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, end, kst[wave], kex[wave], kacc[wave], tab,
                                                         kacc2[kHi ? wave : 0], hi);
         if (k < n) {
             out[k * stride] = v;

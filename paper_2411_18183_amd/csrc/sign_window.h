@@ -214,11 +214,11 @@ __device__ __forceinline__ void load_tables(uint16_t *tab, const uint16_t *__res
 
 // Signature (or finalized plain hash) of each lane's key for a window of 64
 // keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes without
-// a key).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
+// a key); end = where the relation's key bytes end (offsets[n]).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
 // four GF(2^16) components wacc2 (64 entries) accumulates the high word,
 // returned in hi.
 template <int MODE, int NSYM>
-__device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len,
+__device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len, int64_t end,
                                                 int64_t *wst, int32_t *wex, uint32_t *wacc,
                                                 const uint16_t *tab, uint32_t *wacc2, uint32_t &hi)
 {
@@ -249,7 +249,7 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
     const int rem = len - nfull * ASJ_CHUNK;
     if (rem > 0) {
         uint32_t kd[16];
-        asj_load_tail(data, s + (int64_t)nfull * ASJ_CHUNK, rem, kd);
+        asj_load_tail_fast(data, s + (int64_t)nfull * ASJ_CHUNK, rem, end, kd);
         v = chunk_value<MODE, NSYM>(kd, tab, nfull);
         if (kHi) vh = chunk_sig16_hi(kd, tab, nfull);
     }
