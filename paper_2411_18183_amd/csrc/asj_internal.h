@@ -172,6 +172,38 @@ __device__ __forceinline__ void asj_load_tail_fast(const uint8_t *__restrict__ d
     }
 }
 
+// Inclusive prefix maximum across the 64 lanes of a wave (values >= -1):
+// shifts within each row of 16 lanes, then the last lane of a row into the
+// rows after it (DPP row_shr and row_bcast).
+__device__ __forceinline__ int asj_wave_incl_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false)); // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false)); // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false)); // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false)); // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false)); // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false)); // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// Owner of chunk position base + lane in a pass over keys laid out back to
+// back: the last key (lane index) with chunks that starts at or before it.
+// ex_me / n_me: this lane's key's first chunk and chunk count; own: the
+// wave's 64-entry LDS scratch; carry: the owner of the previous pass's last
+// position (-1 before the first pass), updated.
+__device__ __forceinline__ int asj_pass_owner(int ex_me, int n_me, int base, int32_t *own, int &carry)
+{
+    const int lane = threadIdx.x & (ASJ_WAVE - 1);
+    own[lane] = -1;
+    asj_wave_sync();
+    if (n_me > 0 && ex_me >= base && ex_me < base + ASJ_WAVE) own[ex_me - base] = lane;
+    asj_wave_sync();
+    const int o = asj_wave_incl_max(max(own[lane], carry));
+    carry = __builtin_amdgcn_readlane(o, ASJ_WAVE - 1);
+    asj_wave_sync();
+    return min(max(o, 0), ASJ_WAVE - 1);
+}
+
 // Largest i in [0, 64) with ex[i] <= x, for a non-decreasing ex[] in LDS
 // whose first entry is 0.
 __device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)

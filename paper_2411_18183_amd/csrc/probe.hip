@@ -237,8 +237,8 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];
         } else {
-            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, send, wst, wex, wacc, tab, kacc2[kHi ? wave : 0],
-                                              sg_hi);
+            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, send, wst, wex, wacc, wln, tab,
+                                              kacc2[kHi ? wave : 0], sg_hi);
         }
 
         Walk wk;

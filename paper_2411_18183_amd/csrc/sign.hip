@@ -25,6 +25,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
     __shared__ int32_t kex[kWaves][ASJ_WAVE];
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE];
+    __shared__ int32_t kown[kWaves][ASJ_WAVE];
     __shared__ uint32_t kacc2[kHi ? kWaves : 1][ASJ_WAVE];
     asj::load_tables<MODE, kBlock>(tab, gtab);
 
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
             len = (int)(off[k + 1] - s);
         }
         uint32_t hi = 0;
-        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, end, kst[wave], kex[wave], kacc[wave], tab,
+        const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, end, kst[wave], kex[wave], kacc[wave], kown[wave], tab,
                                                         kacc2[kHi ? wave : 0], hi);
         if (k < n) {
             out[k * stride] = v;

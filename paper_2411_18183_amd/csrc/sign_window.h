@@ -214,12 +214,13 @@ __device__ __forceinline__ void load_tables(uint16_t *tab, const uint16_t *__res
 
 // Signature (or finalized plain hash) of each lane's key for a window of 64
 // keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes without
-// a key); end = where the relation's key bytes end (offsets[n]).  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
+// a key); end = where the relation's key bytes end (offsets[n]).  wown is
+// the wave's 64-entry LDS scratch for the pass owners.  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
 // four GF(2^16) components wacc2 (64 entries) accumulates the high word,
 // returned in hi.
 template <int MODE, int NSYM>
 __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len, int64_t end,
-                                                int64_t *wst, int32_t *wex, uint32_t *wacc,
+                                                int64_t *wst, int32_t *wex, uint32_t *wacc, int32_t *wown,
                                                 const uint16_t *tab, uint32_t *wacc2, uint32_t &hi)
 {
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
@@ -233,10 +234,11 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
     if (kHi) wacc2[lane] = 0;
     asj_wave_sync();
     // full chunks of all 64 keys, 64 per pass, one per lane: uniform code
+    int carry = -1;
     for (int base = 0; base < total; base += ASJ_WAVE) {
         const int x = base + lane;
+        const int i = asj_pass_owner(incl - nfull, nfull, base, wown, carry);
         if (x < total) {
-            const int i = asj_find_owner(wex, x);
             const int c = x - wex[i];
             uint32_t kd[16];
             asj_load_full(data, wst[i] + (int64_t)c * ASJ_CHUNK, kd);
