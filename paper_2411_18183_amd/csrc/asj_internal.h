@@ -355,7 +355,7 @@ struct asj_probe_args {
     const uint64_t *nwin;
     int64_t nwin_cap;
     const int64_t *out_seg;
-    int64_t *rows_done;   // int64[njoins], zeroed: probe rows finished per join
+    int64_t *rows_done;   // int64[njoins], zeroed: probe rows finished per join (kept when done_clock is set)
     uint64_t *done_clock; // uint64[njoins] or NULL
 };
 // Signs the probe keys and probes/verifies/compacts in one kernel.

@@ -357,9 +357,10 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
             const unsigned long long rows = __popcll(__ballot(valid));
             if (lane == 0 && rows) {
                 if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + j), (unsigned long long)cands);
-                const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), rows);
-                if (a.done_clock && (int64_t)(before + rows) == a.s_seg[j + 1] - a.s_seg[j])
-                    a.done_clock[j] = wall_clock64();
+                if (a.done_clock) { // the wave that finishes a join's last rows stamps its completion
+                    const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), rows);
+                    if ((int64_t)(before + rows) == a.s_seg[j + 1] - a.s_seg[j]) a.done_clock[j] = wall_clock64();
+                }
             }
         }
     }
