@@ -172,7 +172,10 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
     };
 
     const bool pairs_out = a.kind == ASJ_KIND_INNER || a.kind == ASJ_KIND_LEFT; // the matching pairs themselves
-    const int64_t send = (PRESIGNED || a.n <= 0) ? 0 : a.soff[a.n]; // the probe keys' bytes end here
+    // where the probe keys' and (for the plain join's first-chunk compare)
+    // the build keys' bytes end: short keys are read wide before these
+    const int64_t send = a.n > 0 ? a.soff[a.n] : 0;
+    const int64_t rend = (PLAIN && a.rn > 0) ? a.roff[a.rn] : 0;
     const int kpw = a.keys_per_window;
     const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
     const int64_t stride = (int64_t)gridDim.x * kWaves;
@@ -277,8 +280,8 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
                         asj_load_full(a.rdata, rs, kr);
                         asj_load_full(a.sdata, ss, ks);
                     } else {
-                        asj_load_tail(a.rdata, rs, ls, kr);
-                        asj_load_tail(a.sdata, ss, ls, ks);
+                        asj_load_tail_fast(a.rdata, rs, ls, rend, kr);
+                        asj_load_tail_fast(a.sdata, ss, ls, send, ks);
                     }
 #pragma unroll
                     for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
