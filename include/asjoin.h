@@ -93,6 +93,12 @@ extern "C" {
                                 kernel without signing walks and verifies.  Neither flag means
                                 ASJ_PROBE_FUSED; both flags: ASJ_EINVAL.  The output is the
                                 same either way. */
+#define ASJ_GLOBAL_TABLES 0x400u /* asj_join_batch: every join's table is a segment of one
+                                device-memory slot array.  Without it, a join with at most
+                                10240 build rows gets no segment: each block that probes it
+                                builds the join's table in LDS from the build signatures
+                                (same candidates, same output set).  The split schedule
+                                always uses device-memory tables. */
 
 /* A relation's join attributes: key k is data[offsets[k] .. offsets[k+1]).
  * offsets must be non-decreasing (k = 0..n).  The library reads only
@@ -224,8 +230,10 @@ int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pai
  *               bytes, or NULL to let the library allocate stream-ordered
  *               (with a workspace the call allocates nothing, so it can be
  *               captured into a HIP graph)
- * Each join gets its own table segment (capacity = next power of two >=
- * |R_j| / load_factor, at least 64).  Errors: ASJ_EINVAL, ASJ_ENOMEM,
+ * A join with more than 10240 build rows (every join with
+ * ASJ_GLOBAL_TABLES or the split schedule) gets its own table segment
+ * (capacity = next power of two >= |R_j| / load_factor, at least 64); the
+ * others are probed against tables built in LDS.  Errors: ASJ_EINVAL, ASJ_ENOMEM,
  * ASJ_EUNSUPPORTED, ASJ_EHIP.  The segment arrays are read on the device
  * only: when they do not cover the relations exactly (r_seg[0] = 0,
  * r_seg[njoins] = r.n, no bound decreasing; likewise s_seg), or a segment

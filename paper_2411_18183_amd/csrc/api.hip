@@ -361,7 +361,7 @@ int table_free_impl(asj_table *t)
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
 struct BatchLayout {
-    size_t desc, rows_done, tot, status, win_r, win_s, sig, ssig, slots, bytes;
+    size_t desc, rows_done, tot, status, win_r, win_s, win_l, sig, ssig, slots, bytes;
     int64_t slot_bound, win_r_cap, win_s_cap;
 };
 
@@ -379,13 +379,15 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     L->rows_done = off;
     off = align256(off + sizeof(int64_t) * (size_t)J);
     L->tot = off;
-    off = align256(off + 3 * sizeof(uint64_t));
+    off = align256(off + 4 * sizeof(uint64_t));
     L->status = off;
     off = align256(off + sizeof(int32_t));
     L->win_r = off;
     off = align256(off + sizeof(int32_t) * (size_t)L->win_r_cap);
     L->win_s = off;
     off = align256(off + sizeof(asj_win) * (size_t)L->win_s_cap);
+    L->win_l = off; // LDS-table probe windows: at most as many as probe windows
+    off = align256(off + sizeof(int32_t) * (size_t)L->win_s_cap);
     L->sig = off;
     off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->ssig = off;
@@ -397,7 +399,8 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
 }
 
 int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
-               int *kpw, int *split, int *validate = nullptr, int *kind = nullptr, int *rounds_out = nullptr)
+               int *kpw, int *split, int *validate = nullptr, int *kind = nullptr, int *rounds_out = nullptr,
+               int *local_out = nullptr)
 {
     int rounds_local = 2;
     int *rounds = rounds_out ? rounds_out : &rounds_local;
@@ -408,6 +411,7 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     if (*plain && !*verify) return ASJ_EINVAL;
     if (o.flags & (ASJ_SORTED | ASJ_FINGERPRINT)) return ASJ_EUNSUPPORTED;
     if (validate) *validate = (o.flags & ASJ_VALIDATE) != 0;
+    if (local_out) *local_out = (o.flags & ASJ_GLOBAL_TABLES) == 0;
     const int k = join_kind(o.flags);
     if (k < 0) return ASJ_EINVAL;
     if (kind) *kind = k;
@@ -588,10 +592,11 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int validate, kind;
+    int validate, kind, local;
     int rounds = 2;
-    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind, &rounds);
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind, &rounds, &local);
     if (rc != ASJ_OK) return rc;
+    if (split) local = 0; // the split schedule signs the probe keys first: device-memory tables only
     BatchLayout L;
     if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
     int dev = 0;
@@ -612,6 +617,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int32_t *status = (int32_t *)(ws + L.status);
     int32_t *win_r = (int32_t *)(ws + L.win_r);
     asj_win *win_s = (asj_win *)(ws + L.win_s);
+    int32_t *win_l = (int32_t *)(ws + L.win_l);
     uint32_t *sig_r = (uint32_t *)(ws + L.sig);
     uint32_t *sig_s = (uint32_t *)(ws + L.ssig);
     uint64_t *slots = (uint64_t *)(ws + L.slots);
@@ -619,11 +625,12 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     do {
         hipError_t e;
         tim_begin("batch_plan", st);
-        e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw, desc,
-                                  rows_done, b->out_count, b->cand_count, b->done_clock, tot, status, st);
+        e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw,
+                                  local ? ASJ_LOCAL_ROWS : -1, desc, rows_done, b->out_count, b->cand_count,
+                                  b->done_clock, tot, status, st);
         if (e == hipSuccess)
             e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw, win_r, L.win_r_cap,
-                                      win_s, L.win_s_cap, st);
+                                      win_s, L.win_s_cap, win_l, L.win_s_cap, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
@@ -673,7 +680,16 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
             a.ssig = sig_s;
         }
         tim_begin(plain ? "hash_probe_verify" : (a.ssig ? "probe_verify" : "sign_probe_verify"), st);
-        e = asj_launch_probe(&a, mode, sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        if (local) { // one launch for the windows of both kinds of table
+            a.win_l = win_l;
+            a.nwin_l = tot + 3;
+            a.nwin_l_cap = L.win_s_cap;
+            a.r_seg = b->r_seg;
+            a.rsig = sig_r;
+            e = asj_launch_probe_local(&a, mode, sig.nsym, g_dev[dev].tab, st);
+        } else {
+            e = asj_launch_probe(&a, mode, sig.nsym, g_dev[dev].tab, kProbeGridCap, st);
+        }
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
     } while (0);

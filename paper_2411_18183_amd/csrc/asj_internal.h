@@ -314,10 +314,17 @@ struct asj_win {
 
 struct asj_join_desc {
     uint64_t tbase;  // first slot of the join's segment
-    uint64_t mask;   // segment capacity - 1 (a power of two minus one)
-    int64_t wbase;   // first probe window of the join
-    int64_t wbase_r; // first build window of the join
+    uint64_t mask;   // segment capacity - 1 (a power of two minus one); ~0 for a join with an LDS table
+    int64_t wbase;   // first probe window of the join (device-memory table)
+    int64_t wbase_r; // first build window of the join (device-memory table)
+    int64_t wbase_l; // first probe window of the join (LDS table)
 };
+
+// Batches: a join with at most this many build rows is probed against a
+// table that each probing block builds in LDS from the build signatures
+// (bucketed by mix32, entries sorted by bucket), instead of a segment of the
+// device-memory slot array.
+#define ASJ_LOCAL_ROWS 10240
 
 struct asj_probe_args {
     const uint8_t *rdata;
@@ -357,10 +364,22 @@ struct asj_probe_args {
     const int64_t *out_seg;
     int64_t *rows_done;   // int64[njoins], zeroed: probe rows finished per join (kept when done_clock is set)
     uint64_t *done_clock; // uint64[njoins] or NULL
+    // joins with LDS tables: their probe windows are numbered apart, window w
+    // (w < min(*nwin_l, nwin_l_cap)) belongs to join win_l[w], whose build
+    // rows r_seg[j] .. r_seg[j+1] have signatures rsig[..]
+    const int32_t *win_l;
+    const uint64_t *nwin_l;
+    int64_t nwin_l_cap;
+    const int64_t *r_seg;
+    const uint32_t *rsig;
 };
 // Signs the probe keys and probes/verifies/compacts in one kernel.
 hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st);
+// Batches with LDS tables: the probe windows of every join, those with
+// device-memory tables (a->wins ..) and those with LDS tables (a->win_l ..),
+// in one launch of grid_rounds x the kernel's resident blocks.
+hipError_t asj_launch_probe_local(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, hipStream_t st);
 hipError_t asj_launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t st);
 // Sorts pairs[0 .. min(*count, cap)) by (r_id, s_id); scratch holds
 // asj_sort_scratch_bytes(cap) device bytes.
@@ -373,12 +392,13 @@ hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int gr
 // tot[0] = slots of all segments, tot[1] = build windows, tot[2] = probe
 // windows; win_r / win_s map windows to joins.
 hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
-                                 int64_t slot_cap, float load_factor, int keys_per_window, asj_join_desc *desc,
-                                 int64_t *rows_done, int64_t *out_count, int64_t *cand_count, uint64_t *done_clock,
-                                 uint64_t *tot, int32_t *status, hipStream_t st);
+                                 int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
+                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
+                                 uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st);
 hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
                                  const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
-                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, hipStream_t st);
+                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, int32_t *win_l,
+                                 int64_t win_l_cap, hipStream_t st);
 hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
                                    const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
                                    int32_t *status, hipStream_t st);

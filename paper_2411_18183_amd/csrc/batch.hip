@@ -2,6 +2,9 @@
 // segment of one slot array (Build(R_j, H_sign) of Section 3.2, Figure 2),
 // sized on the device so that no host round trip is needed; the probe side
 // of all joins then runs through the fused probe kernel in one launch.
+// Joins with few build rows (local_rows > 0 and |R_j| <= local_rows) get no
+// segment: the blocks that probe them build their table in LDS from the
+// build signatures, and their probe windows are numbered apart.
 //
 // Rows are handled in windows that never span two joins (64 build rows per
 // insert window, keys_per_window probe rows per probe window), so every
@@ -13,69 +16,78 @@ namespace {
 
 constexpr int kPlanBlock = 1024;
 
-// One block: segment capacities, window counts and their prefix sums,
-// counters zeroed, batch start clock.  Segment arrays that do not cover the
+// One block: segment capacities, window counts (build, probe and
+// LDS-table probe windows) and their prefix sums, counters zeroed, batch
+// start clock.  Segment arrays that do not cover the
 // relations exactly (first bound 0, last bound the row count, no bound
 // decreasing), or segments that would not fit slot_cap slots, set *status
 // to ASJ_EINVAL so that no later kernel of the batch touches the slots.
 __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *__restrict__ r_seg,
                                                                 const int64_t *__restrict__ s_seg, int32_t J,
                                                                 int64_t n_r, int64_t n_s, int64_t slot_cap, float lf,
-                                                                int kpw, asj_join_desc *__restrict__ desc,
+                                                                int kpw, int64_t local_rows,
+                                                                asj_join_desc *__restrict__ desc,
                                                                 int64_t *__restrict__ rows_done,
                                                                 int64_t *__restrict__ out_count,
                                                                 int64_t *__restrict__ cand_count,
                                                                 uint64_t *__restrict__ done_clock,
                                                                 uint64_t *__restrict__ tot, int32_t *__restrict__ status)
 {
-    __shared__ uint64_t scan[3][kPlanBlock];
-    __shared__ uint64_t carry[3];
+    constexpr int Q = 4; // scanned quantities
+    __shared__ uint64_t scan[Q][kPlanBlock];
+    __shared__ uint64_t carry[Q];
     __shared__ int bad;
     const uint64_t start = wall_clock64();
     const int tid = threadIdx.x;
-    if (tid < 3) carry[tid] = 0;
+    if (tid < Q) carry[tid] = 0;
     if (tid == 0) bad = (r_seg[0] != 0 || s_seg[0] != 0 || r_seg[J] != n_r || s_seg[J] != n_s);
     __syncthreads();
     for (int base = 0; base < J; base += kPlanBlock) {
         const int j = base + tid;
-        uint64_t v[3] = {0, 0, 0};
+        uint64_t v[Q] = {0, 0, 0, 0};
         if (j < J) {
             if (r_seg[j + 1] < r_seg[j] || s_seg[j + 1] < s_seg[j]) bad = 1;
             const int64_t nr = max((int64_t)0, r_seg[j + 1] - r_seg[j]);
             const int64_t ns = max((int64_t)0, s_seg[j + 1] - s_seg[j]);
-            uint64_t cap = 64;
-            while ((double)cap * lf < (double)nr) cap <<= 1;
-            v[0] = cap;
-            v[1] = (uint64_t)((nr + ASJ_WAVE - 1) / ASJ_WAVE);
-            v[2] = (uint64_t)((ns + kpw - 1) / kpw);
+            const uint64_t nw = (uint64_t)((ns + kpw - 1) / kpw);
+            if (nr <= local_rows) { // no segment, no build windows: an LDS table
+                v[3] = nw;
+            } else {
+                uint64_t cap = 64;
+                while ((double)cap * lf < (double)nr) cap <<= 1;
+                v[0] = cap;
+                v[1] = (uint64_t)((nr + ASJ_WAVE - 1) / ASJ_WAVE);
+                v[2] = nw;
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 3; q++) scan[q][tid] = v[q];
+        for (int q = 0; q < Q; q++) scan[q][tid] = v[q];
         __syncthreads();
         for (int d = 1; d < kPlanBlock; d <<= 1) { // inclusive scans
-            uint64_t add[3];
+            uint64_t add[Q];
 #pragma unroll
-            for (int q = 0; q < 3; q++) add[q] = tid >= d ? scan[q][tid - d] : 0;
+            for (int q = 0; q < Q; q++) add[q] = tid >= d ? scan[q][tid - d] : 0;
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 3; q++) scan[q][tid] += add[q];
+            for (int q = 0; q < Q; q++) scan[q][tid] += add[q];
             __syncthreads();
         }
         if (j < J) {
             desc[j].tbase = carry[0] + scan[0][tid] - v[0];
-            desc[j].mask = v[0] - 1;
+            desc[j].mask = v[0] - 1; // ~0 for an LDS table
             desc[j].wbase_r = (int64_t)(carry[1] + scan[1][tid] - v[1]);
             desc[j].wbase = (int64_t)(carry[2] + scan[2][tid] - v[2]);
+            desc[j].wbase_l = (int64_t)(carry[3] + scan[3][tid] - v[3]);
             rows_done[j] = 0;
             out_count[j] = 0;
             if (cand_count) cand_count[j] = 0;
             if (done_clock) done_clock[j] = (s_seg[j + 1] <= s_seg[j]) ? start : 0;
         }
         __syncthreads();
-        if (tid < 3) carry[tid] += scan[tid][kPlanBlock - 1];
+        if (tid < Q) carry[tid] += scan[tid][kPlanBlock - 1];
         __syncthreads();
     }
-    if (tid < 3) tot[tid] = bad ? 0 : carry[tid];
+    if (tid < Q) tot[tid] = bad ? 0 : carry[tid];
     if (tid == 0) {
         if (done_clock) done_clock[J] = start;
         *status = (bad || carry[0] > (uint64_t)slot_cap) ? (int32_t)ASJ_EINVAL : (int32_t)ASJ_OK;
@@ -84,25 +96,29 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
 
 // Empty slots up to the planned total, then the window maps (block b
 // writes the windows of joins b, b + gridDim.x, ...): build window -> join,
-// and for every probe window its join, first row and row count.  Every
-// write stays inside the caller's capacities whatever the segment arrays
-// hold.
+// for every probe window its join, first row and row count, and LDS-table
+// probe window -> join.  Every write stays inside the caller's capacities
+// whatever the segment arrays hold.
 __global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap, const uint64_t *__restrict__ tot,
                                   const asj_join_desc *__restrict__ desc, const int64_t *__restrict__ s_seg,
                                   int32_t J, int kpw, int32_t *__restrict__ win_r, int64_t win_r_cap,
-                                  asj_win *__restrict__ win_s, int64_t win_s_cap)
+                                  asj_win *__restrict__ win_s, int64_t win_s_cap, int32_t *__restrict__ win_l,
+                                  int64_t win_l_cap)
 {
     const int64_t n = min(slot_cap, (int64_t)tot[0]);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         slots[i] = ASJ_EMPTY_SLOT;
     const int64_t nr = min(win_r_cap, (int64_t)tot[1]);
     const int64_t ns = min(win_s_cap, (int64_t)tot[2]);
+    const int64_t nl = min(win_l_cap, (int64_t)tot[3]);
     for (int j = blockIdx.x; j < J; j += gridDim.x) {
-        const int64_t r0 = desc[j].wbase_r, s0 = desc[j].wbase;
+        const int64_t r0 = desc[j].wbase_r, s0 = desc[j].wbase, l0 = desc[j].wbase_l;
         const int64_t r1 = j + 1 < J ? desc[j + 1].wbase_r : nr;
         const int64_t s1 = j + 1 < J ? desc[j + 1].wbase : ns;
+        const int64_t l1 = j + 1 < J ? desc[j + 1].wbase_l : nl;
         const int64_t first = s_seg[j], end = s_seg[j + 1];
         for (int64_t w = r0 + threadIdx.x; w < min(r1, nr); w += blockDim.x) win_r[w] = j;
+        for (int64_t w = l0 + threadIdx.x; w < min(l1, nl); w += blockDim.x) win_l[w] = j;
         for (int64_t w = s0 + threadIdx.x; w < min(s1, ns); w += blockDim.x) {
             asj_win e;
             e.join = j;
@@ -170,23 +186,27 @@ int grid_for(int64_t n, int block, int cap)
 } // namespace
 
 hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
-                                 int64_t slot_cap, float load_factor, int keys_per_window, asj_join_desc *desc,
-                                 int64_t *rows_done, int64_t *out_count, int64_t *cand_count, uint64_t *done_clock,
-                                 uint64_t *tot, int32_t *status, hipStream_t st)
+                                 int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
+                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
+                                 uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st)
 {
     if (keys_per_window < 1 || keys_per_window > ASJ_WAVE) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s, slot_cap,
-                       load_factor, keys_per_window, desc, rows_done, out_count, cand_count, done_clock, tot, status);
+                       load_factor, keys_per_window, local_rows, desc, rows_done, out_count, cand_count, done_clock,
+                       tot, status);
     return hipGetLastError();
 }
 
 hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
                                  const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
-                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, hipStream_t st)
+                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, int32_t *win_l,
+                                 int64_t win_l_cap, hipStream_t st)
 {
-    const int g = grid_for(slot_cap > njoins * 256LL ? slot_cap : njoins * 256LL, 256, 16384);
+    // a bounded grid: the fill loop strides, and a batch whose joins all
+    // have LDS tables fills nothing
+    const int g = grid_for(slot_cap > njoins * 256LL ? slot_cap : njoins * 256LL, 256, 2048);
     hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, slots, slot_cap, tot, desc, s_seg, njoins,
-                       keys_per_window, win_r, win_r_cap, win_s, win_s_cap);
+                       keys_per_window, win_r, win_r_cap, win_s, win_s_cap, win_l, win_l_cap);
     return hipGetLastError();
 }
 
@@ -195,7 +215,9 @@ hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t
                                    int32_t *status, hipStream_t st)
 {
     if (m <= 0 || win_r_cap <= 0) return hipSuccess;
-    const dim3 g(grid_for(win_r_cap * ASJ_WAVE, 256, 16384)), b(256);
+    // bounded grid (the window loop strides): a batch whose joins all have
+    // LDS tables inserts nothing
+    const dim3 g(grid_for(win_r_cap * ASJ_WAVE, 256, 2048)), b(256);
     hipLaunchKernelGGL(insert_batch_kernel<1>, g, b, 0, st, sig, m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
     hipLaunchKernelGGL(insert_batch_kernel<0>, g, b, 0, st, sig, m, r_seg, desc, win_r, tot, win_r_cap, slots, status);
     return hipGetLastError();

@@ -33,19 +33,38 @@
 // the window map, probes that join's table segment, appends to that join's
 // output segment, and the wave that finishes a join's last probe row stamps
 // its completion clock.
+// A batch's joins with few build rows are probed against LDS tables (the
+// LOCAL form, which takes all of a batch's windows in one launch): the grid
+// is split between the two kinds of window in proportion to their counts; a
+// block of the LDS-table part takes an equal share of those windows and,
+// for every join in its share, first builds the join's table in LDS from the
+// build signatures (a bucket per value of the low bits of mix32(signature),
+// entries ordered by bucket with a counting sort), so a walk is a few LDS
+// reads and no device-memory table is written, initialised or read.
 #include "sign_window.h"
 
 namespace {
 
 // Block size: 8 waves when the kernel signs (one copy of the GF tables in
 // LDS serves more waves), 4 waves when the signatures are given (no tables;
-// the smaller block fits the register-limited wave count per CU exactly).
-template <int PRESIGNED>
+// the smaller block fits the register-limited wave count per CU exactly),
+// 16 with an LDS table (one block per CU holds the tables and the join's
+// table).  stage = result pairs staged per wave; flushed once more than
+// stage - 64 wait.
+template <int PRESIGNED, int LOCAL>
 struct Shape {
-    static constexpr int block = PRESIGNED ? 256 : 512;
+    static constexpr int block = LOCAL ? 1024 : PRESIGNED ? 256 : 512;
     static constexpr int waves = block / ASJ_WAVE;
+    static constexpr int stage = LOCAL ? 128 : 256;
 };
-constexpr int kStage = 256; // staged result pairs per wave; flushed once more than kStage - 64 wait
+// LDS table buckets: the plain baseline keeps no signature per entry, so
+// every entry of its bucket is a candidate; the LDS the signatures would
+// take holds four times the buckets instead (0.6 entries per bucket at the
+// size limit).
+template <int PLAIN>
+struct LocalBuckets {
+    static constexpr int value = PLAIN ? 16384 : 4096;
+};
 
 typedef uint64_t asj_u64x2 __attribute__((ext_vector_type(2), aligned(16)));
 typedef uint64_t asj_u64x2a8 __attribute__((ext_vector_type(2), aligned(8)));
@@ -98,6 +117,22 @@ __device__ __forceinline__ bool next_candidate(const uint64_t *__restrict__ slot
     return has;
 }
 
+// Next candidate of a lane's LDS-table bucket (entries cur .. end); true
+// with *r = the entry's build row within its join.
+template <int PLAIN>
+__device__ __forceinline__ bool next_local(const uint32_t *lsig, const uint16_t *lrow, uint32_t sg, uint32_t &cur,
+                                           uint32_t end, uint32_t &r)
+{
+    while (cur < end) {
+        const uint32_t i = cur++;
+        if (PLAIN || lsig[i] == sg) {
+            r = lrow[i];
+            return true;
+        }
+    }
+    return false;
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
 #pragma unroll
@@ -105,14 +140,16 @@ __device__ __forceinline__ int wave_sum(int v)
     return v;
 }
 
-template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH, int PRESIGNED>
+template <int MODE, int NSYM, int PLAIN, int VERIFY, int BATCH, int PRESIGNED, int LOCAL>
 // At most 128 registers (4 waves per SIMD): above that only one block fits a
 // CU.
-__global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_probe_args a,
-                                                                         const uint16_t *__restrict__ gtab)
+__global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_kernel(
+    asj_probe_args a, const uint16_t *__restrict__ gtab)
 {
-    constexpr int kBlock = Shape<PRESIGNED>::block;
-    constexpr int kWaves = Shape<PRESIGNED>::waves;
+    constexpr int kBlock = Shape<PRESIGNED, LOCAL>::block;
+    constexpr int kWaves = Shape<PRESIGNED, LOCAL>::waves;
+    constexpr int kStage = Shape<PRESIGNED, LOCAL>::stage;
+    constexpr int kBuckets = LocalBuckets<PLAIN>::value;
     // four GF(2^16) components: the table holds the low word (components 1,
     // 2), a candidate must also match the build row's high word
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4 && !PRESIGNED;
@@ -124,6 +161,12 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
     __shared__ uint32_t kacc[kWaves][ASJ_WAVE]; // signature accumulators, then mismatch flags
     __shared__ uint32_t kacc2[kHi ? kWaves : 1][ASJ_WAVE]; // high-word accumulators
     __shared__ asj_pair kout[kWaves][kStage];   // result pairs staged before one output reservation
+    // LDS table of the current join: bucket b holds entries lend[b-1] ..
+    // lend[b] (lend[-1] = 0) with the build rows' signatures and rows
+    __shared__ uint32_t lend[LOCAL ? kBuckets : 1];
+    __shared__ uint32_t lsig[LOCAL && !PLAIN ? ASJ_LOCAL_ROWS : 1];
+    __shared__ uint16_t lrow[LOCAL ? ASJ_LOCAL_ROWS : 1];
+    __shared__ uint32_t lwsum[LOCAL ? kWaves : 1];
 
     if (*a.table_status != 0 || (a.probe_status && *a.probe_status != 0)) { // the whole grid leaves
         if (blockIdx.x == 0) {
@@ -133,6 +176,35 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         }
         return;
     }
+    const int kpw = a.keys_per_window;
+    // Windows of this launch: every ngrid * kWaves-th device-table window
+    // from gblk * kWaves + wave on (gblk = block index, ngrid = grid) and,
+    // LOCAL, the share [w_lo, w_hi) of the LDS-table windows.  LOCAL splits
+    // the grid between the two kinds in proportion to their window counts:
+    // blocks 0 .. gl - 1 take equal shares of the LDS-table windows, the
+    // others the device-table windows (a one-block grid takes both).  A
+    // block without windows leaves at once, before it loads the tables.
+    int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
+    int64_t w_lo = 0, w_hi = 0, gblk = blockIdx.x, ngrid = gridDim.x;
+    bool do_glob = true;
+    if (LOCAL) {
+        const int64_t nl = min((int64_t)*a.nwin_l, a.nwin_l_cap);
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        int64_t gl = 0;
+        if (nl > 0) gl = nwin == 0 ? G : min(G - 1, max((int64_t)1, (G * nl + (nl + nwin) / 2) / (nl + nwin)));
+        if (G == 1) {
+            w_hi = nl;
+        } else if (b < gl) {
+            w_lo = nl * b / gl;
+            w_hi = nl * (b + 1) / gl;
+            do_glob = false;
+        } else {
+            gblk = b - gl;
+            ngrid = G - gl;
+        }
+    }
+    if (do_glob && gblk * kWaves >= nwin) do_glob = false;
+    if (!do_glob && w_lo >= w_hi) return;
     if (!PRESIGNED) asj::load_tables<MODE, kBlock>(tab, gtab);
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / ASJ_WAVE);
@@ -176,19 +248,27 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
     // the build keys' bytes end: short keys are read wide before these
     const int64_t send = a.n > 0 ? a.soff[a.n] : 0;
     const int64_t rend = (PLAIN && a.rn > 0) ? a.roff[a.rn] : 0;
-    const int kpw = a.keys_per_window;
-    const int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
-    const int64_t stride = (int64_t)gridDim.x * kWaves;
     // What starts the next window -- its map entry (batch), or its keys'
-    // offsets and ids (single join) -- is requested while the current window
-    // is processed, so a window does not begin with a chain of dependent
-    // loads.  Vector loads (every lane asks for the same entry), so that the
-    // requests wait in the in-order vector queue and not in the counter the
-    // LDS operations share with scalar loads.
+    // offsets and ids (single join, LDS-table windows) -- is requested while
+    // the current window is processed, so a window does not begin with a
+    // chain of dependent loads.  Vector loads (every lane asks for the same
+    // entry), so that the requests wait in the in-order vector queue and not
+    // in the counter the LDS operations share with scalar loads.
     asj_win pre_w = {0, 0, 0};
     int64_t pre_o0 = 0, pre_o1 = 0;
     int32_t pre_id = 0;
-    auto prefetch = [&](int64_t w) {
+    int64_t pre_end = 0; // LDS-table windows: end of the current join's probe rows
+    // w = the next window (lw, an LDS-table window: its first row, < 0 for none)
+    auto prefetch = [&](int64_t w, bool lw) {
+        if (LOCAL && lw) {
+            const int64_t kk = w + lane;
+            if (w >= 0 && lane < kpw && kk < pre_end) {
+                pre_o0 = a.soff[kk];
+                pre_o1 = a.soff[kk + 1];
+                pre_id = a.sids ? a.sids[kk] : (int32_t)kk;
+            }
+            return;
+        }
         if (w >= nwin) return;
         if (BATCH) {
             pre_w = a.wins[w];
@@ -201,30 +281,19 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
             }
         }
     };
-    prefetch((int64_t)blockIdx.x * kWaves + wave);
-    for (int64_t win = (int64_t)blockIdx.x * kWaves + wave; win < nwin; win += stride) {
-        // the window's rows, its join and table segment
-        int64_t k0 = win * kpw;
-        int rows = (int)min((int64_t)kpw, a.n - k0);
-        int j = 0;
-        const uint64_t *slots = a.slots;
-        uint64_t mask = a.mask;
+
+    // One window: probe rows k0 .. k0 + rows (of join j in batch mode)
+    // against the table segment (slots, mask) or, lw, the block's LDS table
+    // of the join, whose build rows start at row rbase; the next window's
+    // prefetch is issued once this one's rows are read.
+    auto window = [&](int j, int64_t k0, int rows, const uint64_t *slots, uint64_t mask, int64_t rbase,
+                      int64_t next, bool lw) {
+        const int64_t k = k0 + lane;
+        const bool valid = lane < rows && k >= 0 && k < a.n;
         int64_t ss = 0;
         int ls = 0;
         int32_t sid = 0;
-        if (BATCH) {
-            j = __builtin_amdgcn_readfirstlane(pre_w.join);
-            rows = __builtin_amdgcn_readfirstlane(pre_w.rows);
-            k0 = ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(pre_w.first >> 32)) << 32) |
-                 (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)pre_w.first);
-            const asj_join_desc d = a.desc[j];
-            slots = a.slots + d.tbase;
-            mask = d.mask;
-            stage_join = j;
-        }
-        const int64_t k = k0 + lane;
-        const bool valid = lane < rows && k >= 0 && k < a.n;
-        if (BATCH) {
+        if (BATCH && !(LOCAL && lw)) {
             if (valid) {
                 ss = a.soff[k];
                 ls = (int)(a.soff[k + 1] - ss);
@@ -235,7 +304,7 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
             ls = (int)(pre_o1 - pre_o0);
             sid = pre_id;
         }
-        prefetch(win + stride);
+        prefetch(next, lw);
         uint32_t sg = 0, sg_hi = 0;
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];
@@ -248,11 +317,23 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
         wk.h = asj_mix32(sg) & mask;
         wk.qb = ~0ull;
         wk.walking = valid;
+        uint32_t lcur = 0, lstop = 0; // LDS table: the lane's bucket
+        if (LOCAL && lw && valid) {
+            const uint32_t bk = asj_mix32(sg) & (uint32_t)(kBuckets - 1);
+            lcur = bk ? lend[bk - 1] : 0u;
+            lstop = lend[bk];
+        }
         int lane_cand = 0;
         bool matched = false; // this lane's key has a verified (or, unverified, signature-equal) match
         for (;;) {
             uint32_t r = 0;
-            const bool walked = next_candidate<PLAIN>(slots, mask, sg, wk, r);
+            bool walked;
+            if (LOCAL && lw) {
+                walked = next_local<PLAIN>(lsig, lrow, sg, lcur, lstop, r);
+                r += (uint32_t)rbase;
+            } else {
+                walked = next_candidate<PLAIN>(slots, mask, sg, wk, r);
+            }
             const uint64_t hm = __ballot(walked);
             if (hm == 0) break;
             bool has = walked;
@@ -308,10 +389,10 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
                         if (L >= ASJ_CHUNK) {
                             // chunk c covers [64c, 64c + 64); the last one ends at
                             // the key's end, [L - 64, L), overlapping its neighbour
-                            const int64_t k0 = (c + 1) * ASJ_CHUNK <= L ? (int64_t)c * ASJ_CHUNK : (int64_t)(L - ASJ_CHUNK);
+                            const int64_t c0 = (c + 1) * ASJ_CHUNK <= L ? (int64_t)c * ASJ_CHUNK : (int64_t)(L - ASJ_CHUNK);
                             uint32_t kr[16], ks[16];
-                            asj_load_full(a.rdata, wrs[i] + k0, kr);
-                            asj_load_full(a.sdata, wst[i] + k0, ks);
+                            asj_load_full(a.rdata, wrs[i] + c0, kr);
+                            asj_load_full(a.sdata, wst[i] + c0, ks);
 #pragma unroll
                             for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
                         } else {
@@ -355,16 +436,116 @@ __global__ __launch_bounds__(Shape<PRESIGNED>::block, 4) void probe_kernel(asj_p
             if (nstage > kStage - ASJ_WAVE) flush();
         }
         if (BATCH) {
-            flush(); // a join's pairs are all out before its rows are counted done
+            // a join's pairs are all out before its rows are counted done;
+            // an LDS-table block stays on one join until its share of the
+            // join's windows is done, so it flushes per window only for the
+            // completion clocks
+            if (!(LOCAL && lw) || a.done_clock) flush();
             const int cands = wave_sum(lane_cand);
-            const unsigned long long rows = __popcll(__ballot(valid));
-            if (lane == 0 && rows) {
+            const unsigned long long nrows = __popcll(__ballot(valid));
+            if (lane == 0 && nrows) {
                 if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + j), (unsigned long long)cands);
                 if (a.done_clock) { // the wave that finishes a join's last rows stamps its completion
-                    const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), rows);
-                    if ((int64_t)(before + rows) == a.s_seg[j + 1] - a.s_seg[j]) a.done_clock[j] = wall_clock64();
+                    const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), nrows);
+                    if ((int64_t)(before + nrows) == a.s_seg[j + 1] - a.s_seg[j]) a.done_clock[j] = wall_clock64();
                 }
             }
+        }
+    };
+
+    if (LOCAL) {
+        // this block's share of the LDS-table windows, join by join
+        for (int64_t w = w_lo; w < w_hi;) { // block-uniform
+            const int j = __builtin_amdgcn_readfirstlane(a.win_l[w]);
+            const int64_t wb = a.desc[j].wbase_l;
+            const int64_t s0 = a.s_seg[j], s1 = a.s_seg[j + 1];
+            const int64_t r0 = a.r_seg[j];
+            const int nr = (int)min((int64_t)ASJ_LOCAL_ROWS, max((int64_t)0, a.r_seg[j + 1] - r0));
+            const int64_t w_end = min(w_hi, wb + (s1 - s0 + kpw - 1) / kpw);
+            if (w_end <= w) break; // a map entry outside its join's windows: nothing sane to do
+            // this wave's first window of the join
+            pre_end = s1;
+            if (w + wave < w_end) prefetch(s0 + (w + wave - wb) * kpw, true);
+            // the join's table: its signatures read once into registers, bucket
+            // counts, their exclusive prefix sums, then every entry placed at
+            // its bucket's next position (which leaves lend[b] at the end of
+            // bucket b)
+            constexpr int kPer = (ASJ_LOCAL_ROWS + kBlock - 1) / kBlock;
+            uint32_t rsg[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const int i = (int)threadIdx.x + q * kBlock;
+                rsg[q] = i < nr ? a.rsig[r0 + i] : 0u;
+            }
+            __syncthreads(); // the previous join's lookups are over
+            for (int b = threadIdx.x; b < kBuckets; b += kBlock) lend[b] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; q++)
+                if ((int)threadIdx.x + q * kBlock < nr) atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+            __syncthreads();
+            {
+                constexpr int per = kBuckets / kBlock; // consecutive buckets per thread
+                uint32_t c[per], sum = 0;
+#pragma unroll
+                for (int q = 0; q < per; q++) {
+                    c[q] = lend[threadIdx.x * per + q];
+                    sum += c[q];
+                }
+                const int incl = asj_wave_incl_scan((int)sum);
+                if (lane == ASJ_WAVE - 1) lwsum[wave] = (uint32_t)incl;
+                __syncthreads();
+                uint32_t before = 0;
+                for (int q = 0; q < wave; q++) before += lwsum[q];
+                uint32_t run = before + (uint32_t)incl - sum;
+#pragma unroll
+                for (int q = 0; q < per; q++) {
+                    lend[threadIdx.x * per + q] = run;
+                    run += c[q];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                const int i = (int)threadIdx.x + q * kBlock;
+                if (i < nr) {
+                    const uint32_t pos = atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+                    if (!PLAIN) lsig[pos] = rsg[q];
+                    lrow[pos] = (uint16_t)i;
+                }
+            }
+            __syncthreads();
+            stage_join = j;
+            for (int64_t win = w + wave; win < w_end; win += kWaves) {
+                const int64_t k0 = s0 + (win - wb) * kpw;
+                const int64_t nxt = win + kWaves < w_end ? k0 + (int64_t)kWaves * kpw : -1;
+                window(j, k0, (int)min((int64_t)kpw, s1 - k0), nullptr, 0, r0, nxt, true);
+            }
+            flush(); // the next join's pairs go to another output segment
+            w = w_end;
+        }
+    }
+    if (do_glob) {
+        const int64_t stride = ngrid * kWaves;
+        prefetch(gblk * kWaves + wave, false);
+        for (int64_t win = gblk * kWaves + wave; win < nwin; win += stride) {
+            // the window's rows, its join and table segment
+            int64_t k0 = win * kpw;
+            int rows = (int)min((int64_t)kpw, a.n - k0);
+            int j = 0;
+            const uint64_t *slots = a.slots;
+            uint64_t mask = a.mask;
+            if (BATCH) {
+                j = __builtin_amdgcn_readfirstlane(pre_w.join);
+                rows = __builtin_amdgcn_readfirstlane(pre_w.rows);
+                k0 = ((int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(pre_w.first >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)pre_w.first);
+                const asj_join_desc d = a.desc[j];
+                slots = a.slots + d.tbase;
+                mask = d.mask;
+                stage_join = j;
+            }
+            window(j, k0, rows, slots, mask, 0, win + stride, false);
         }
     }
     flush();
@@ -391,25 +572,44 @@ template <int MODE, int NSYM, int PLAIN, int VERIFY, int PRESIGNED>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
     const int64_t nwin = a->njoins > 0 ? a->nwin_cap : (a->n + a->keys_per_window - 1) / a->keys_per_window;
-    constexpr int kBlock = Shape<PRESIGNED>::block;
-    constexpr int kWaves = Shape<PRESIGNED>::waves;
+    constexpr int kBlock = Shape<PRESIGNED, 0>::block;
+    constexpr int kWaves = Shape<PRESIGNED, 0>::waves;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (a->grid_rounds > 0) { // the grid in rounds of resident blocks
         static const int64_t res_batch = resident_blocks(
-            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED>), kBlock);
+            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED, 0>), kBlock);
         static const int64_t res_single = resident_blocks(
-            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED>), kBlock);
+            reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED, 0>), kBlock);
         const int64_t resident = a->njoins > 0 ? res_batch : res_single;
         if (resident > 0 && blocks > resident * a->grid_rounds) blocks = resident * a->grid_rounds;
     }
     if (blocks < 1) blocks = 1;
     if (a->njoins > 0)
-        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED, 0>), dim3((unsigned)blocks),
                            dim3(kBlock), 0, st, *a, tab);
     else
-        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED, 0>), dim3((unsigned)blocks),
                            dim3(kBlock), 0, st, *a, tab);
+    return hipGetLastError();
+}
+
+// All windows of a batch with LDS tables: grid_rounds x the resident blocks
+// (one per compute unit), split between the two kinds of window on the
+// device.
+template <int MODE, int NSYM, int PLAIN, int VERIFY>
+hipError_t launch_local(const asj_probe_args *a, const uint16_t *tab, hipStream_t st)
+{
+    constexpr int kBlock = Shape<0, 1>::block;
+    static const int64_t resident =
+        resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, 0, 1>), kBlock);
+    if (resident <= 0) return hipErrorInvalidValue; // the kernel does not fit a compute unit
+    int64_t blocks = resident * (a->grid_rounds > 0 ? a->grid_rounds : 1);
+    const int64_t most = (a->nwin_cap + a->nwin_l_cap) / Shape<0, 1>::waves + 2;
+    if (blocks > most) blocks = most;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, 0, 1>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                       st, *a, tab);
     return hipGetLastError();
 }
 
@@ -443,5 +643,24 @@ hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, cons
     if (mode == ASJ_MODE_SIG16 && nsym == 1) return launch_sig<ASJ_MODE_SIG16, 1>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch_sig<ASJ_MODE_SIG8, 4>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 2) return launch_sig<ASJ_MODE_SIG8, 2>(a, tab, grid_cap, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t asj_launch_probe_local(const asj_probe_args *a_in, int mode, int nsym, const uint16_t *tab, hipStream_t st)
+{
+    asj_probe_args fixed = *a_in;
+    if (fixed.keys_per_window < 1 || fixed.keys_per_window > ASJ_WAVE) fixed.keys_per_window = ASJ_WAVE;
+    const asj_probe_args *a = &fixed;
+    if (!a->win_l || !a->nwin_l || !a->r_seg || !a->rsig || !a->wins || !a->nwin || a->njoins < 1 || a->ssig)
+        return hipErrorInvalidValue;
+    if (a->plain) return launch_local<ASJ_MODE_PLAIN, 1, 1, 1>(a, tab, st);
+#define ASJ_LOCAL_SIG(M, N)                                                                                       \
+    if (mode == M && nsym == N)                                                                                   \
+        return a->verify ? launch_local<M, N, 0, 1>(a, tab, st) : launch_local<M, N, 0, 0>(a, tab, st);
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG16, 2)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG16, 1)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG8, 4)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG8, 2)
+#undef ASJ_LOCAL_SIG
     return hipErrorInvalidValue;
 }

@@ -33,7 +33,9 @@ def flatten(wl, joins):
     return wl.from_keys(rk, rid), wl.from_keys(sk, sid), np.array(r_seg), np.array(s_seg)
 
 
-SCHED = {"split": 0x8, "fused": 0x4}
+# fused: joins with at most 10240 build rows get LDS tables (every join in
+# these small batches); fused_global: device-memory tables for all
+SCHED = {"split": 0x8, "fused": 0x4, "fused_global": 0x4 | 0x400}
 
 
 @pytest.mark.parametrize("sched", sorted(SCHED))
@@ -53,6 +55,58 @@ def test_batch_matches_oracle_and_single_joins(A, oracle, wl, sched):
         assert np.array_equal(oracle.sort_pairs(alone.cpu().numpy()), oracle.sort_pairs(got)), k
     start = clock[-1]
     assert start > 0 and (clock[:-1] >= start).all()
+
+
+def concat(wl, parts):
+    """Workloads -> one batch: flattened relations (row-local ids) and segments."""
+    def cat(rels):
+        lens = np.concatenate([r.lengths() for r in rels])
+        data = np.concatenate([r.data[:r.offsets[-1]] for r in rels] + [np.zeros(16, np.uint8)])
+        off = np.zeros(len(lens) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        return wl.Relation(data, off, np.concatenate([r.ids for r in rels]))
+    seg = lambda rels: np.concatenate([[0], np.cumsum([r.n for r in rels])]).astype(np.int64)
+    return cat([p.R for p in parts]), cat([p.S for p in parts]), seg([p.R for p in parts]), seg([p.S for p in parts])
+
+
+KINDS = {"inner": 0, "semi": 0x40, "anti": 0x80, "left": 0x100}
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("kind", sorted(KINDS))
+def test_batch_lds_tables_beside_device_tables(A, oracle, wl, kind, plain):
+    """Joins on both sides of the LDS-table limit (10240 build rows) in one
+    batch, one of them with every key repeated about 20 times on both sides
+    (long runs of equal signatures in one bucket), probe sides long enough
+    that a join's windows are shared by several blocks: every join equals
+    the oracle's, and the run with device-memory tables for all joins."""
+    sizes = [(1, 300, 24), (700, 5000, 70), (10239, 12000, 130), (10240, 12000, 9), (10241, 9000, 64),
+             (25000, 30000, 33), (64, 64, 200)]
+    parts = []
+    for i, (m, n, L) in enumerate(sizes):
+        alphabet = np.frombuffer(b"ab", dtype=np.uint8) if L == 9 else None  # 512 distinct keys
+        parts.append(wl.fixed_length(seed=40 + i, m=m, n=n, key_len=L, copy_frac=0.3, alphabet=alphabet))
+    Rf, Sf, r_seg, s_seg = concat(wl, parts)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    flags = KINDS[kind] | (A.ASJ_PLAIN if plain else 0)
+    caps = None
+    if kind != "inner":
+        caps = np.diff(s_seg) + 16
+    else:
+        caps = np.array([21 * n + 64 for _, n, _ in sizes])
+    got, oseg, counts, _, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags)
+    ref, rseg, rcounts, _, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags | A.ASJ_GLOBAL_TABLES)
+    goth, refh = got.cpu().numpy(), ref.cpu().numpy()
+    for k, w in enumerate(parts):
+        want = oracle.join_nested(w.R, w.S) if kind == "inner" and w.R.n * w.S.n < 4_000_000 else None
+        if kind == "inner" and want is None:
+            want, _ = oracle.join_signature(w.R, w.S)
+        elif kind != "inner":
+            want = oracle.join_variant(w.R, w.S, kind)
+        mine = oracle.sort_pairs(goth[oseg[k]:oseg[k] + counts[k]])
+        assert counts[k] == len(want) and np.array_equal(mine, want), (kind, plain, k)
+        assert rcounts[k] == counts[k], (kind, plain, k)
+        assert np.array_equal(oracle.sort_pairs(refh[rseg[k]:rseg[k] + rcounts[k]]), mine), (kind, plain, k)
 
 
 def test_batch_empty_joins_duplicates_and_caller_workspace(A, oracle, wl):
