@@ -157,11 +157,11 @@ int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *
 // out_hi / stride: see asj_launch_sign (four GF(2^16) components only).
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
                            hipStream_t st, const int32_t *status = nullptr, uint32_t *out_hi = nullptr,
-                           int stride = 1)
+                           int stride = 1, const asj_batch_prep *prep = nullptr)
 {
-    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status);
+    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status, nullptr, 1, prep);
     return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st,
-                           status, out_hi, stride);
+                           status, out_hi, stride, prep);
 }
 
 bool sig64(asj_sig_params s) { return s.f == 16 && s.nsym == 4; }
@@ -628,15 +628,16 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw,
                                   local ? ASJ_LOCAL_ROWS : -1, desc, rows_done, b->out_count, b->cand_count,
                                   b->done_clock, tot, status, st);
-        if (e == hipSuccess)
-            e = asj_launch_batch_prep(slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw, win_r, L.win_r_cap,
-                                      win_s, L.win_s_cap, win_l, L.win_s_cap, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        // the slot fill and window maps are written by the signature kernel
+        // (or, without build keys, a kernel of their own)
+        asj_batch_prep prep = {slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw,
+                               win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap};
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status);
+        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin("insert", st);

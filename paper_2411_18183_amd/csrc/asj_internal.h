@@ -281,9 +281,12 @@ hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
 // out[k * stride] = signature (plain hash) of key k; with four GF(2^16)
 // components that is the low word (components 1, 2) and out_hi[k * stride]
 // receives the high word (components 3, 4).
+// prep (may be NULL): the batch's slot fill and window maps, written by the
+// kernel's blocks before they sign (one launch fewer per batch).
+struct asj_batch_prep;
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
                            int grid_cap, hipStream_t st, const int32_t *status = nullptr,
-                           uint32_t *out_hi = nullptr, int stride = 1);
+                           uint32_t *out_hi = nullptr, int stride = 1, const asj_batch_prep *prep = nullptr);
 // Sets *status = ASJ_EINVAL unless off[0] >= 0 and off[] never decreases.
 hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, hipStream_t st);
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
@@ -325,6 +328,54 @@ struct asj_join_desc {
 // (bucketed by mix32, entries sorted by bucket), instead of a segment of the
 // device-memory slot array.
 #define ASJ_LOCAL_ROWS 10240
+
+// A batch's preparation after its plan: empty slots up to the planned total,
+// then the window maps (block b writes the windows of joins b, b + nblocks,
+// ...): build window -> join, for every probe window its join, first row and
+// row count, and LDS-table probe window -> join.  Every write stays inside
+// the capacities whatever the segment arrays hold.
+struct asj_batch_prep {
+    uint64_t *slots;
+    int64_t slot_cap;
+    const uint64_t *tot; // planned totals: slots, build windows, probe windows, LDS-table windows
+    const asj_join_desc *desc;
+    const int64_t *s_seg;
+    int32_t njoins;
+    int32_t kpw;
+    int32_t *win_r;
+    int64_t win_r_cap;
+    asj_win *win_s;
+    int64_t win_s_cap;
+    int32_t *win_l;
+    int64_t win_l_cap;
+};
+
+__device__ inline void asj_batch_prep_run(const asj_batch_prep &p, int64_t block, int64_t nblocks, int tid,
+                                          int nthreads)
+{
+    const int64_t n = p.slot_cap < (int64_t)p.tot[0] ? p.slot_cap : (int64_t)p.tot[0];
+    for (int64_t i = block * nthreads + tid; i < n; i += nblocks * nthreads) p.slots[i] = ASJ_EMPTY_SLOT;
+    const int64_t nr = p.win_r_cap < (int64_t)p.tot[1] ? p.win_r_cap : (int64_t)p.tot[1];
+    const int64_t ns = p.win_s_cap < (int64_t)p.tot[2] ? p.win_s_cap : (int64_t)p.tot[2];
+    const int64_t nl = p.win_l_cap < (int64_t)p.tot[3] ? p.win_l_cap : (int64_t)p.tot[3];
+    for (int64_t j = block; j < p.njoins; j += nblocks) {
+        const asj_join_desc d = p.desc[j];
+        const int64_t r1 = j + 1 < p.njoins ? p.desc[j + 1].wbase_r : nr;
+        const int64_t s1 = j + 1 < p.njoins ? p.desc[j + 1].wbase : ns;
+        const int64_t l1 = j + 1 < p.njoins ? p.desc[j + 1].wbase_l : nl;
+        const int64_t first = p.s_seg[j], end = p.s_seg[j + 1];
+        for (int64_t w = d.wbase_r + tid; w < (r1 < nr ? r1 : nr); w += nthreads) p.win_r[w] = (int32_t)j;
+        for (int64_t w = d.wbase_l + tid; w < (l1 < nl ? l1 : nl); w += nthreads) p.win_l[w] = (int32_t)j;
+        for (int64_t w = d.wbase + tid; w < (s1 < ns ? s1 : ns); w += nthreads) {
+            asj_win e;
+            e.join = (int32_t)j;
+            e.first = first + (w - d.wbase) * p.kpw;
+            const int64_t left = end - e.first;
+            e.rows = (int32_t)(left < p.kpw ? left : p.kpw);
+            p.win_s[w] = e;
+        }
+    }
+}
 
 struct asj_probe_args {
     const uint8_t *rdata;
@@ -395,10 +446,7 @@ hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int
                                  int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
                                  asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
                                  uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st);
-hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
-                                 const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
-                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, int32_t *win_l,
-                                 int64_t win_l_cap, hipStream_t st);
+hipError_t asj_launch_batch_prep(const asj_batch_prep *p, hipStream_t st);
 hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
                                    const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
                                    int32_t *status, hipStream_t st);

@@ -94,39 +94,11 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
     }
 }
 
-// Empty slots up to the planned total, then the window maps (block b
-// writes the windows of joins b, b + gridDim.x, ...): build window -> join,
-// for every probe window its join, first row and row count, and LDS-table
-// probe window -> join.  Every write stays inside the caller's capacities
-// whatever the segment arrays hold.
-__global__ void batch_prep_kernel(uint64_t *__restrict__ slots, int64_t slot_cap, const uint64_t *__restrict__ tot,
-                                  const asj_join_desc *__restrict__ desc, const int64_t *__restrict__ s_seg,
-                                  int32_t J, int kpw, int32_t *__restrict__ win_r, int64_t win_r_cap,
-                                  asj_win *__restrict__ win_s, int64_t win_s_cap, int32_t *__restrict__ win_l,
-                                  int64_t win_l_cap)
+// The preparation (asj_batch_prep_run) when the build side has no key to
+// sign (otherwise the signature kernel does it).
+__global__ void batch_prep_kernel(asj_batch_prep p)
 {
-    const int64_t n = min(slot_cap, (int64_t)tot[0]);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        slots[i] = ASJ_EMPTY_SLOT;
-    const int64_t nr = min(win_r_cap, (int64_t)tot[1]);
-    const int64_t ns = min(win_s_cap, (int64_t)tot[2]);
-    const int64_t nl = min(win_l_cap, (int64_t)tot[3]);
-    for (int j = blockIdx.x; j < J; j += gridDim.x) {
-        const int64_t r0 = desc[j].wbase_r, s0 = desc[j].wbase, l0 = desc[j].wbase_l;
-        const int64_t r1 = j + 1 < J ? desc[j + 1].wbase_r : nr;
-        const int64_t s1 = j + 1 < J ? desc[j + 1].wbase : ns;
-        const int64_t l1 = j + 1 < J ? desc[j + 1].wbase_l : nl;
-        const int64_t first = s_seg[j], end = s_seg[j + 1];
-        for (int64_t w = r0 + threadIdx.x; w < min(r1, nr); w += blockDim.x) win_r[w] = j;
-        for (int64_t w = l0 + threadIdx.x; w < min(l1, nl); w += blockDim.x) win_l[w] = j;
-        for (int64_t w = s0 + threadIdx.x; w < min(s1, ns); w += blockDim.x) {
-            asj_win e;
-            e.join = j;
-            e.first = first + (w - s0) * kpw;
-            e.rows = (int32_t)min((int64_t)kpw, end - e.first);
-            win_s[w] = e;
-        }
-    }
+    asj_batch_prep_run(p, blockIdx.x, gridDim.x, threadIdx.x, blockDim.x);
 }
 
 // Lane l of build window w inserts row r_seg[j] + 64 (w - wbase_r) + l of
@@ -197,16 +169,14 @@ hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int
     return hipGetLastError();
 }
 
-hipError_t asj_launch_batch_prep(uint64_t *slots, int64_t slot_cap, const uint64_t *tot, const asj_join_desc *desc,
-                                 const int64_t *s_seg, int32_t njoins, int keys_per_window, int32_t *win_r,
-                                 int64_t win_r_cap, asj_win *win_s, int64_t win_s_cap, int32_t *win_l,
-                                 int64_t win_l_cap, hipStream_t st)
+hipError_t asj_launch_batch_prep(const asj_batch_prep *p, hipStream_t st)
 {
+    if (p->kpw < 1) return hipErrorInvalidValue;
     // a bounded grid: the fill loop strides, and a batch whose joins all
     // have LDS tables fills nothing
-    const int g = grid_for(slot_cap > njoins * 256LL ? slot_cap : njoins * 256LL, 256, 2048);
-    hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, slots, slot_cap, tot, desc, s_seg, njoins,
-                       keys_per_window, win_r, win_r_cap, win_s, win_s_cap, win_l, win_l_cap);
+    const int64_t work = p->slot_cap > p->njoins * 256LL ? p->slot_cap : p->njoins * 256LL;
+    const int g = grid_for(work, 256, 2048);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3(g), dim3(256), 0, st, *p);
     return hipGetLastError();
 }
 

@@ -11,15 +11,18 @@ constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / ASJ_WAVE;
 
 // out[k * stride] = signature of key k (its low word with four GF(2^16)
-// components, whose high word goes to out_hi[k * stride]).
+// components, whose high word goes to out_hi[k * stride]).  With has_prep
+// the blocks first do their part of a batch's preparation.
 template <int MODE, int NSYM>
 __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
                                                       const int64_t *__restrict__ off, int64_t n,
                                                       uint32_t *__restrict__ out, uint32_t *__restrict__ out_hi,
                                                       int stride, const uint16_t *__restrict__ gtab,
-                                                      const int32_t *__restrict__ status)
+                                                      const int32_t *__restrict__ status, asj_batch_prep prep,
+                                                      int has_prep)
 {
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
+    if (has_prep) asj_batch_prep_run(prep, blockIdx.x, gridDim.x, threadIdx.x, kBlock);
     if (status && *status != 0) return; // the inputs failed validation: read no key (same for every thread)
     __shared__ uint16_t tab[asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
@@ -53,36 +56,38 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
 
 template <int MODE, int NSYM>
 hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride, const uint16_t *tab, int grid_cap,
-                  const int32_t *status, hipStream_t st)
+                  const int32_t *status, const asj_batch_prep *prep, hipStream_t st)
 {
+    const asj_batch_prep none = {};
     const int64_t nwin = (k->n + ASJ_WAVE - 1) / ASJ_WAVE;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((sign_kernel<MODE, NSYM>), dim3((unsigned)blocks), dim3(kBlock), 0, st, k->data, k->offsets,
-                       k->n, out, out_hi, stride, tab, status);
+                       k->n, out, out_hi, stride, tab, status, prep ? *prep : none, prep ? 1 : 0);
     return hipGetLastError();
 }
 
 } // namespace
 
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap,
-                           hipStream_t st, const int32_t *status, uint32_t *out_hi, int stride)
+                           hipStream_t st, const int32_t *status, uint32_t *out_hi, int stride,
+                           const asj_batch_prep *prep)
 {
-    if (k->n == 0) return hipSuccess;
+    if (k->n == 0) return prep ? asj_launch_batch_prep(prep, st) : hipSuccess;
     if (stride < 1) return hipErrorInvalidValue;
     if (mode == ASJ_MODE_SIG16 && nsym == 4) {
         if (!out_hi) return hipErrorInvalidValue;
-        return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, st);
+        return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, prep, st);
     }
     if (mode == ASJ_MODE_SIG16 && nsym == 2)
-        return launch<ASJ_MODE_SIG16, 2>(k, out, nullptr, stride, tab, grid_cap, status, st);
+        return launch<ASJ_MODE_SIG16, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 1)
-        return launch<ASJ_MODE_SIG16, 1>(k, out, nullptr, stride, tab, grid_cap, status, st);
+        return launch<ASJ_MODE_SIG16, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 4)
-        return launch<ASJ_MODE_SIG8, 4>(k, out, nullptr, stride, tab, grid_cap, status, st);
+        return launch<ASJ_MODE_SIG8, 4>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 2)
-        return launch<ASJ_MODE_SIG8, 2>(k, out, nullptr, stride, tab, grid_cap, status, st);
-    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, nullptr, stride, tab, grid_cap, status, st);
+        return launch<ASJ_MODE_SIG8, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
+    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
     return hipErrorInvalidValue;
 }
