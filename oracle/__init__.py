@@ -211,6 +211,9 @@ def join_signature(R, S, f=16, nsym=2, verify=True, cap=None):
 #   semi   S |x R : one pair (-1, s_id) per probe row with at least one match
 #   anti   S |> R : one pair (-1, s_id) per probe row with no match
 #   left   S =x R : T plus (-1, s_id) for every probe row with no match
+#   right  S x= R : T plus (r_id, -1) for every build row that no probe row
+#                   matches
+#   full   S =x= R: T plus both kinds of unmatched row
 # Matches are exact key equality (or, with verify=False, signature equality,
 # the paper-literal reading).
 # ---------------------------------------------------------------------------
@@ -232,9 +235,22 @@ def _matched_rows(R, S, verify=True):
     return matched
 
 
+def _matched_build_rows(R, S, verify=True):
+    """Boolean per build row: does some probe row match it?  (Row indexes as
+    build ids, as in _matched_rows.)"""
+    data, off, _, m = _as_rel(R)
+    rows = (data, off, np.arange(m, dtype=np.int32))
+    pairs = join_hash(rows, S) if verify else join_signature(rows, S, verify=False)[0]
+    matched = np.zeros(m, dtype=bool)
+    matched[pairs[:, 0]] = True
+    return matched
+
+
 def join_variant(R, S, kind: str, verify=True):
-    """Semi ('semi'), anti ('anti') or left outer ('left') join of S with R,
-    as sorted (r_id, s_id) pairs (r_id = -1 for the probe-only rows)."""
+    """Semi ('semi'), anti ('anti'), left outer ('left'), right outer
+    ('right') or full outer ('full') join of S with R, as sorted (r_id, s_id)
+    pairs (r_id = -1 for the probe-only rows, s_id = -1 for the build-only
+    rows)."""
     ids = _probe_ids(S)
     matched = _matched_rows(R, S, verify)
     lonely = np.stack([np.full(int((~matched).sum()), -1, np.int32), ids[~matched]], axis=1)
@@ -242,7 +258,14 @@ def join_variant(R, S, kind: str, verify=True):
         return sort_pairs(np.stack([np.full(int(matched.sum()), -1, np.int32), ids[matched]], axis=1))
     if kind == "anti":
         return sort_pairs(lonely)
-    if kind == "left":
+    if kind in ("left", "right", "full"):
         inner = join_nested(R, S) if verify else join_signature(R, S, verify=False)[0]
-        return sort_pairs(np.concatenate([inner.reshape(-1, 2), lonely]))
+        parts = [inner.reshape(-1, 2)]
+        if kind in ("left", "full"):
+            parts.append(lonely)
+        if kind in ("right", "full"):
+            rids = _probe_ids(R)
+            rm = _matched_build_rows(R, S, verify)
+            parts.append(np.stack([rids[~rm], np.full(int((~rm).sum()), -1, np.int32)], axis=1))
+        return sort_pairs(np.concatenate(parts))
     raise ValueError(kind)

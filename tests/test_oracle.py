@@ -394,16 +394,19 @@ def test_fixed_length_workload_structure(oracle, wl):
 
 
 def _brute_variant(R_keys, S_keys, S_ids, kind):
-    """Semi / anti / left outer join by explicit Python loops over the keys."""
+    """Semi / anti / left, right and full outer join by explicit Python loops
+    over the keys (build ids = build row indexes)."""
     out = []
     for s, sid in zip(S_keys, S_ids):
         hits = [r for r, rk in enumerate(R_keys) if rk == s]
         if kind == "semi" and hits:
             out.append((-1, sid))
-        elif kind in ("anti", "left") and not hits:
+        elif kind in ("anti", "left", "full") and not hits:
             out.append((-1, sid))
-        if kind == "left":
+        if kind in ("left", "right", "full"):
             out += [(r, sid) for r in hits]
+    if kind in ("right", "full"):
+        out += [(r, -1) for r, rk in enumerate(R_keys) if rk not in S_keys]
     return sorted(out)
 
 
@@ -413,7 +416,8 @@ def test_join_variants_equal_brute_force(oracle, wl, seed):
     R_keys = [w.R.key(i) for i in range(w.R.n)]
     S_keys = [w.S.key(i) for i in range(w.S.n)]
     S_ids = [int(x) for x in w.S.ids]
-    for kind in ("semi", "anti", "left"):
+    assert [int(x) for x in w.R.ids] == list(range(w.R.n))  # build ids are row indexes here
+    for kind in ("semi", "anti", "left", "right", "full"):
         got = [tuple(map(int, p)) for p in oracle.join_variant(w.R, w.S, kind)]
         assert got == _brute_variant(R_keys, S_keys, S_ids, kind), kind
 
@@ -427,3 +431,9 @@ def test_join_variant_invariants(oracle, wl):
     assert set(semi[:, 1]) == set(inner[:, 1])
     assert np.array_equal(left, oracle.sort_pairs(np.concatenate([inner, anti])))
     assert len(semi) == 400 and (semi[:, 0] == -1).all()      # the recipe's copies are the matches
+    right, full = (oracle.join_variant(w.R, w.S, k) for k in ("right", "full"))
+    lonely_r = right[right[:, 1] == -1]
+    assert len(lonely_r) + len(set(inner[:, 0])) == w.R.n   # every build row is matched or listed once
+    assert not set(lonely_r[:, 0]) & set(inner[:, 0])
+    assert np.array_equal(right, oracle.sort_pairs(np.concatenate([inner, lonely_r])))
+    assert np.array_equal(full, oracle.sort_pairs(np.concatenate([inner, anti, lonely_r])))
