@@ -83,11 +83,21 @@ extern "C" {
  *   ASJ_SEMI        S semi-join R: (-1, s_id) once per probe row with a match
  *   ASJ_ANTI        S anti-join R: (-1, s_id) for each probe row without one
  *   ASJ_LEFT_OUTER  every inner pair plus (-1, s_id) for each unmatched row
+ *   ASJ_RIGHT_OUTER every inner pair plus (r_id, -1) for each build row that
+ *                   no probe row matches (per asj_probe / asj_join call)
+ *   ASJ_LEFT_OUTER | ASJ_RIGHT_OUTER  the full outer join: both
+ * (left, right and semi-joins are named as future work in Section 5).
  * |T| counts the pairs written.  A match is key equality, or signature
- * equality under ASJ_NO_VERIFY.  More than one kind: ASJ_EINVAL. */
+ * equality under ASJ_NO_VERIFY.  Any other combination: ASJ_EINVAL.  The
+ * right and full outer joins are offered by asj_join, asj_probe and
+ * asj_join_batch (the server and asj_join_host: ASJ_EUNSUPPORTED); the
+ * unmatched build rows are written after every probe row has been
+ * processed, so overlapping asj_probe calls on one such table are fine but
+ * each call reports the build rows that its own probe rows left unmatched. */
 #define ASJ_SEMI 0x40u
 #define ASJ_ANTI 0x80u
 #define ASJ_LEFT_OUTER 0x100u
+#define ASJ_RIGHT_OUTER 0x800u
 #define ASJ_PROBE_SPLIT 0x8u /* probe schedule: the probe keys are signed by the signature kernel
                                 into a device scratch array first (4 bytes per key), then a probe
                                 kernel without signing walks and verifies.  Neither flag means

@@ -34,6 +34,7 @@ ASJ_VALIDATE = 0x20
 ASJ_SEMI = 0x40
 ASJ_ANTI = 0x80
 ASJ_LEFT_OUTER = 0x100
+ASJ_RIGHT_OUTER = 0x800
 ASJ_FINGERPRINT = 0x200
 ASJ_GLOBAL_TABLES = 0x400
 

@@ -125,10 +125,15 @@ int resolve_sig(asj_sig_params p, asj_sig_params *out)
 // Join kind from the flags; -1 when more than one is set.
 int join_kind(uint32_t flags)
 {
-    const int n = ((flags & ASJ_SEMI) != 0) + ((flags & ASJ_ANTI) != 0) + ((flags & ASJ_LEFT_OUTER) != 0);
-    if (n > 1) return -1;
-    return (flags & ASJ_SEMI) ? ASJ_KIND_SEMI : (flags & ASJ_ANTI) ? ASJ_KIND_ANTI
-                              : (flags & ASJ_LEFT_OUTER) ? ASJ_KIND_LEFT : ASJ_KIND_INNER;
+    const bool semi = flags & ASJ_SEMI, anti = flags & ASJ_ANTI;
+    const bool left = flags & ASJ_LEFT_OUTER, right = flags & ASJ_RIGHT_OUTER;
+    if ((int)semi + (int)anti + (int)(left || right) > 1) return -1;
+    if (semi) return ASJ_KIND_SEMI;
+    if (anti) return ASJ_KIND_ANTI;
+    if (left && right) return ASJ_KIND_FULL;
+    if (left) return ASJ_KIND_LEFT;
+    if (right) return ASJ_KIND_RIGHT;
+    return ASJ_KIND_INNER;
 }
 
 // Table load factor, probe keys per window and probe schedule (1 = split:
@@ -327,6 +332,20 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
         }
         a.probe_status = pstatus;
     }
+    // right and full outer joins: a byte per build row, set by the probe
+    // for the matched rows; the others are appended after the probe
+    uint8_t *rmatch = nullptr;
+    if (asj_kind_marks_build(t->kind) && t->r.n > 0) {
+        const int64_t words = (t->r.n + 3) / 4;
+        e = alloc_async(&rmatch, (size_t)words * 4, st);
+        if (e == hipSuccess) e = asj_launch_fill_i32((int32_t *)rmatch, words, 0, st);
+        if (e != hipSuccess) {
+            if (rmatch) (void)hipFreeAsync(rmatch, st);
+            if (pstatus) (void)hipFreeAsync(pstatus, st);
+            return hip_fail(e);
+        }
+        a.rmatch = rmatch;
+    }
     uint32_t *ssig = nullptr;
     if (!t->split || s->n == 0) {
         tim_begin(t->plain ? "hash_probe_verify" : t->fp ? "fp_probe_verify" : "sign_probe_verify", st);
@@ -347,6 +366,13 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
         }
         if (ssig) (void)hipFreeAsync(ssig, st);
     }
+    if (e == hipSuccess && rmatch) {
+        tim_begin("unmatched_build", st);
+        e = asj_launch_unmatched_build(rmatch, t->r.ids, t->r.n, out, out_cap, out_count, t->status, pstatus, 0,
+                                       nullptr, nullptr, st);
+        tim_end(st);
+    }
+    if (rmatch) (void)hipFreeAsync(rmatch, st);
     if (pstatus) (void)hipFreeAsync(pstatus, st);
     return e == hipSuccess ? ASJ_OK : hip_fail(e);
 }
@@ -361,7 +387,7 @@ int table_free_impl(asj_table *t)
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
 struct BatchLayout {
-    size_t desc, rows_done, tot, status, win_r, win_s, win_l, sig, ssig, slots, bytes;
+    size_t desc, rows_done, tot, status, win_r, win_s, win_l, rmatch, sig, ssig, slots, bytes;
     int64_t slot_bound, win_r_cap, win_s_cap;
 };
 
@@ -388,6 +414,8 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     off = align256(off + sizeof(asj_win) * (size_t)L->win_s_cap);
     L->win_l = off; // LDS-table probe windows: at most as many as probe windows
     off = align256(off + sizeof(int32_t) * (size_t)L->win_s_cap);
+    L->rmatch = off; // right and full outer joins: a byte per build row
+    off = align256(off + 4 * (size_t)((n_build + 3) / 4));
     L->sig = off;
     off = align256(off + sizeof(uint32_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->ssig = off;
@@ -436,6 +464,7 @@ int asj_resolve_opts(const asj_opts *opts, int64_t n_build, asj_resolved *r)
     if (o.flags & ASJ_FINGERPRINT) return ASJ_EUNSUPPORTED; // single joins only
     r->kind = join_kind(o.flags);
     if (r->kind < 0) return ASJ_EINVAL;
+    if (asj_kind_marks_build(r->kind)) return ASJ_EUNSUPPORTED; // right / full outer: asj_join, asj_probe, batches
     r->sig = asj_sig_params{16, 2};
     if (!r->plain) {
         const int rc = resolve_sig(o.sig, &r->sig);
@@ -634,8 +663,10 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         // the slot fill and window maps are written by the signature kernel
         // (or, without build keys, a kernel of their own)
+        uint8_t *rmatch = asj_kind_marks_build(kind) ? ws + L.rmatch : nullptr;
         asj_batch_prep prep = {slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw,
-                               win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap};
+                               win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap,
+                               (uint32_t *)rmatch, rmatch ? (b->r.n + 3) / 4 : 0};
         tim_begin(plain ? "hash_build" : "sign_build", st);
         e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep);
         tim_end(st);
@@ -672,6 +703,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         a.rows_done = rows_done;
         a.done_clock = b->done_clock;
         a.grid_rounds = rounds;
+        a.rmatch = rmatch;
         const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
         if (split && b->s.n > 0) {
             tim_begin(plain ? "hash_S" : "sign_S", st);
@@ -693,6 +725,13 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         }
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        if (rmatch) { // right and full outer joins: the build rows without a match
+            tim_begin("unmatched_build", st);
+            e = asj_launch_unmatched_build(rmatch, b->r.ids, b->r.n, b->out, 0, b->out_count, status, nullptr,
+                                           b->njoins, b->r_seg, b->out_seg, st);
+            tim_end(st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        }
     } while (0);
     if (owned) (void)hipFreeAsync(ws, st);
     return out_rc;

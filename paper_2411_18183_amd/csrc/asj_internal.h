@@ -305,7 +305,10 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
 // (64 rows each, for the inserts) and its probe rows windows wbase ..
 // (keys_per_window rows each, for the probe kernel).
 // Join kinds (the flags ASJ_SEMI, ASJ_ANTI, ASJ_LEFT_OUTER).
-enum { ASJ_KIND_INNER = 0, ASJ_KIND_SEMI = 1, ASJ_KIND_ANTI = 2, ASJ_KIND_LEFT = 3 };
+enum { ASJ_KIND_INNER = 0, ASJ_KIND_SEMI = 1, ASJ_KIND_ANTI = 2, ASJ_KIND_LEFT = 3, ASJ_KIND_RIGHT = 4, ASJ_KIND_FULL = 5 };
+// The kinds that list the build rows without a match (their probes mark
+// matched build rows, and a kernel appends the others afterwards).
+inline bool asj_kind_marks_build(int kind) { return kind == ASJ_KIND_RIGHT || kind == ASJ_KIND_FULL; }
 
 // One probe window of a batch: its join, its first probe row and how many
 // rows it holds (1 .. keys_per_window).
@@ -348,6 +351,8 @@ struct asj_batch_prep {
     int64_t win_s_cap;
     int32_t *win_l;
     int64_t win_l_cap;
+    uint32_t *rmatch;     // right and full outer joins: the matched-row bytes, zeroed here
+    int64_t rmatch_words; // in 4-byte words
 };
 
 __device__ inline void asj_batch_prep_run(const asj_batch_prep &p, int64_t block, int64_t nblocks, int tid,
@@ -355,6 +360,8 @@ __device__ inline void asj_batch_prep_run(const asj_batch_prep &p, int64_t block
 {
     const int64_t n = p.slot_cap < (int64_t)p.tot[0] ? p.slot_cap : (int64_t)p.tot[0];
     for (int64_t i = block * nthreads + tid; i < n; i += nblocks * nthreads) p.slots[i] = ASJ_EMPTY_SLOT;
+    if (p.rmatch)
+        for (int64_t i = block * nthreads + tid; i < p.rmatch_words; i += nblocks * nthreads) p.rmatch[i] = 0u;
     const int64_t nr = p.win_r_cap < (int64_t)p.tot[1] ? p.win_r_cap : (int64_t)p.tot[1];
     const int64_t ns = p.win_s_cap < (int64_t)p.tot[2] ? p.win_s_cap : (int64_t)p.tot[2];
     const int64_t nl = p.win_l_cap < (int64_t)p.tot[3] ? p.win_l_cap : (int64_t)p.tot[3];
@@ -400,7 +407,8 @@ struct asj_probe_args {
     int verify;
     int keys_per_window; // probe keys per wave window (1..64)
     int grid_rounds;     // > 0: grid = grid_rounds x the kernel's resident blocks (capped by grid_cap)
-    int kind;            // ASJ_KIND_*: inner, semi, anti or left outer join of the probe relation
+    int kind;            // ASJ_KIND_*: inner, semi, anti, left, right or full outer join
+    uint8_t *rmatch;     // right and full outer joins: one byte per build row, zeroed; set for matched rows
     // batch of joins (njoins > 0): probe row k belongs to join j with
     // s_seg[j] <= k < s_seg[j+1]; its table is slots[desc[j].tbase ..] with
     // mask desc[j].mask, its output out[out_seg[j] .. out_seg[j+1]) and its
@@ -427,6 +435,14 @@ struct asj_probe_args {
 // Signs the probe keys and probes/verifies/compacts in one kernel.
 hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st);
+// Right and full outer joins: (r_id, -1) for every build row r < m with
+// rmatch[r] == 0, appended to the output like the probe kernel's pairs.
+// Batch (njoins > 0): row r belongs to join j with r_seg[j] <= r <
+// r_seg[j+1] and goes to out[out_seg[j] ..] with out_count[j].  Nothing
+// happens when a status word is set (the probe then reported -1).
+hipError_t asj_launch_unmatched_build(const uint8_t *rmatch, const int32_t *rids, int64_t m, asj_pair *out, int64_t cap,
+                                      int64_t *out_count, const int32_t *status1, const int32_t *status2,
+                                      int32_t njoins, const int64_t *r_seg, const int64_t *out_seg, hipStream_t st);
 // Batches with LDS tables: the probe windows of every join, those with
 // device-memory tables (a->wins ..) and those with LDS tables (a->win_l ..),
 // in one launch of grid_rounds x the kernel's resident blocks.

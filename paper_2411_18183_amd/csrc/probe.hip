@@ -243,7 +243,8 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         nstage = 0;
     };
 
-    const bool pairs_out = a.kind == ASJ_KIND_INNER || a.kind == ASJ_KIND_LEFT; // the matching pairs themselves
+    // the matching pairs themselves (every kind but the semi- and anti-join)
+    const bool pairs_out = a.kind != ASJ_KIND_SEMI && a.kind != ASJ_KIND_ANTI;
     // where the probe keys' and (for the plain join's first-chunk compare)
     // the build keys' bytes end: short keys are read wide before these
     const int64_t send = a.n > 0 ? a.soff[a.n] : 0;
@@ -411,6 +412,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
             }
             // stage the survivors in LDS; output space is reserved per flush
             matched = matched || ok;
+            if (ok && a.rmatch) a.rmatch[r] = 1; // right and full outer joins: this build row has a match
             const bool emit = ok && pairs_out;
             const uint64_t m = __ballot(emit);
             if (emit) {
@@ -422,8 +424,8 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
             nstage += __popcll(m);
             if (nstage > kStage - ASJ_WAVE) flush();
         }
-        if (a.kind != ASJ_KIND_INNER) {
-            // semi: matched probe rows; anti and left outer: unmatched ones
+        if (a.kind != ASJ_KIND_INNER && a.kind != ASJ_KIND_RIGHT) {
+            // semi: matched probe rows; anti, left and full outer: unmatched ones
             const bool emit = valid && (a.kind == ASJ_KIND_SEMI ? matched : !matched);
             const uint64_t m = __ballot(emit);
             if (emit) {
@@ -553,6 +555,65 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         atomicAdd((unsigned long long *)a.cand_count, (unsigned long long)wave_cand);
 }
 
+// (r_id, -1) for each build row without a match (see
+// asj_launch_unmatched_build): a wave takes 64 consecutive rows and reserves
+// output space with one atomic per join among its rows.
+__global__ __launch_bounds__(256) void unmatched_build_kernel(const uint8_t *__restrict__ rmatch,
+                                                              const int32_t *__restrict__ rids, int64_t m,
+                                                              asj_pair *__restrict__ out, int64_t cap,
+                                                              int64_t *__restrict__ out_count,
+                                                              const int32_t *__restrict__ status1,
+                                                              const int32_t *__restrict__ status2, int32_t J,
+                                                              const int64_t *__restrict__ r_seg,
+                                                              const int64_t *__restrict__ out_seg)
+{
+    if ((status1 && *status1 != 0) || (status2 && *status2 != 0)) return;
+    const int lane = threadIdx.x % ASJ_WAVE;
+    const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / ASJ_WAVE);
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / ASJ_WAVE) + threadIdx.x / ASJ_WAVE;
+    for (int64_t base = wave0 * ASJ_WAVE; base < m; base += nwaves * ASJ_WAVE) {
+        const int64_t r = base + lane;
+        const bool emit = r < m && rmatch[r] == 0;
+        int j = 0;
+        if (J > 0 && emit) { // the join: r_seg[lo] <= r < r_seg[hi] throughout (r_seg[0] = 0, r_seg[J] = m)
+            int lo = 0, hi = J;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (r_seg[mid] <= r) lo = mid;
+                else hi = mid;
+            }
+            j = lo;
+        }
+        uint64_t pend = __ballot(emit);
+        while (pend) { // one reservation per join among the wave's rows
+            const int leader = __ffsll((unsigned long long)pend) - 1;
+            const int jl = __shfl(j, leader, ASJ_WAVE);
+            const bool mine = emit && j == jl;
+            const uint64_t grp = __ballot(mine);
+            int64_t *cnt = out_count + (J > 0 ? jl : 0);
+            int64_t o0 = 0, cp = cap;
+            if (J > 0) {
+                o0 = out_seg[jl];
+                cp = out_seg[jl + 1] - o0;
+            }
+            unsigned long long b0 = 0;
+            if (lane == leader) b0 = atomicAdd((unsigned long long *)cnt, (unsigned long long)__popcll(grp));
+            b0 = __shfl(b0, leader, ASJ_WAVE);
+            if (mine) {
+                const int64_t idx = (int64_t)b0 + __popcll(grp & lanemask_lt);
+                if (idx < cp) {
+                    asj_pair p;
+                    p.r_id = rids ? rids[r] : (int32_t)r;
+                    p.s_id = -1;
+                    out[o0 + idx] = p;
+                }
+            }
+            pend &= ~grp;
+        }
+    }
+}
+
 // Blocks of `kernel` that the device holds at once (blocks per compute unit
 // from the occupancy calculator x compute units); 0 when the runtime cannot
 // say.
@@ -644,6 +705,19 @@ hipError_t asj_launch_probe(const asj_probe_args *a_in, int mode, int nsym, cons
     if (mode == ASJ_MODE_SIG8 && nsym == 4) return launch_sig<ASJ_MODE_SIG8, 4>(a, tab, grid_cap, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 2) return launch_sig<ASJ_MODE_SIG8, 2>(a, tab, grid_cap, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t asj_launch_unmatched_build(const uint8_t *rmatch, const int32_t *rids, int64_t m, asj_pair *out, int64_t cap,
+                                      int64_t *out_count, const int32_t *status1, const int32_t *status2,
+                                      int32_t njoins, const int64_t *r_seg, const int64_t *out_seg, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    if (!rmatch || !out_count || (njoins > 0 && (!r_seg || !out_seg))) return hipErrorInvalidValue;
+    int64_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(unmatched_build_kernel, dim3((unsigned)blocks), dim3(256), 0, st, rmatch, rids, m, out, cap,
+                       out_count, status1, status2, njoins, r_seg, out_seg);
+    return hipGetLastError();
 }
 
 hipError_t asj_launch_probe_local(const asj_probe_args *a_in, int mode, int nsym, const uint16_t *tab, hipStream_t st)

@@ -363,6 +363,7 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
     if (!o.dry_run && !t) return ASJ_EINVAL;
     if (t && !t->plain && t->sig.f == 16 && t->sig.nsym == 4) return ASJ_EUNSUPPORTED; // 64-bit signatures
     if (t && t->fp) return ASJ_EUNSUPPORTED;                                            // fingerprint control
+    if (t && asj_kind_marks_build(t->kind)) return ASJ_EUNSUPPORTED; // right / full outer: per-call build marks
     if (o.slots <= 0) o.slots = 4;
     if (o.hbm_budget <= 0) o.hbm_budget = 200ll << 30;
     if (o.max_batch_keys <= 0) o.max_batch_keys = 4ll << 20;

@@ -69,7 +69,7 @@ def concat(wl, parts):
     return cat([p.R for p in parts]), cat([p.S for p in parts]), seg([p.R for p in parts]), seg([p.S for p in parts])
 
 
-KINDS = {"inner": 0, "semi": 0x40, "anti": 0x80, "left": 0x100}
+KINDS = {"inner": 0, "semi": 0x40, "anti": 0x80, "left": 0x100, "right": 0x800, "full": 0x900}
 
 
 @pytest.mark.parametrize("plain", [False, True])
@@ -91,7 +91,7 @@ def test_batch_lds_tables_beside_device_tables(A, oracle, wl, kind, plain):
     flags = KINDS[kind] | (A.ASJ_PLAIN if plain else 0)
     caps = None
     if kind != "inner":
-        caps = np.diff(s_seg) + 16
+        caps = np.diff(s_seg) + np.diff(r_seg) + 16
     else:
         caps = np.array([21 * n + 64 for _, n, _ in sizes])
     got, oseg, counts, _, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags)

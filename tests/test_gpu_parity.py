@@ -474,7 +474,7 @@ def test_validate_flag_batch(A, oracle, wl):
     assert (counts == -1).all()
 
 
-KINDS = {"semi": 0x40, "anti": 0x80, "left": 0x100}
+KINDS = {"semi": 0x40, "anti": 0x80, "left": 0x100, "right": 0x800, "full": 0x900}
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -501,8 +501,8 @@ def test_join_variants_batch_and_served(A, oracle, wl):
     import torch
     b = wl.batch(scale=0.002, njoins=8)
     R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
-    for kind in ("anti", "left"):
-        caps = 2 * np.diff(b.s_seg) + 16
+    for kind in ("anti", "left", "right", "full"):
+        caps = 2 * np.diff(b.s_seg) + np.diff(b.r_seg) + 16
         out, oseg, counts, _, _ = A.join_batch(R, S, b.r_seg, b.s_seg, caps=caps, flags=KINDS[kind])
         outh = out.cpu().numpy()
         for k in range(b.njoins):
@@ -527,3 +527,39 @@ def test_two_join_kinds_rejected(A, wl):
     w = wl.random_small(1, m=10, n=10)
     with pytest.raises(A.AsjError):
         gpu_join(A, w.R, w.S, flags=KINDS["semi"] | KINDS["anti"])
+
+
+@pytest.mark.parametrize("kind", ["right", "full"])
+def test_outer_build_side_kinds_rejected_by_server_and_host_join(A, wl, kind):
+    """The right and full outer joins list build rows that a call's probe rows
+    left unmatched; the server (many overlapping requests on one table) and
+    the host-memory join (S in pieces) do not offer them."""
+    w = wl.random_small(2, m=50, n=50)
+    t = A.asj_build(A.DeviceKeys.from_host(w.R), flags=KINDS[kind])
+    with pytest.raises(A.AsjError) as ei:
+        A.Server(t, slots=1)
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+    t.free()
+    import torch
+    out = torch.empty((16, 2), dtype=torch.int32).pin_memory()
+    with pytest.raises(A.AsjError) as ei:
+        A.asj_join_host(A.HostKeys.from_host(w.R), A.HostKeys.from_host(w.S), out, flags=KINDS[kind])
+    assert ei.value.code == A.ASJ_EUNSUPPORTED
+
+
+def test_right_outer_probe_calls_report_their_own_unmatched_rows(A, oracle, wl):
+    """One table, two probe relations: each asj_probe call lists the build rows
+    that its own probe rows did not match."""
+    import torch
+    w = wl.random_small(4, m=300, n=200, max_len=6, alphabet=b"ab")
+    w2 = wl.random_small(5, m=10, n=150, max_len=6, alphabet=b"ab")
+    t = A.asj_build(A.DeviceKeys.from_host(w.R), flags=KINDS["right"])
+    for S in (w.S, w2.S, w.S):
+        want = oracle.join_variant(w.R, S, "right")
+        out = torch.empty((len(want) + 8, 2), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        A.asj_probe(t, A.DeviceKeys.from_host(S), out, cnt)
+        n = int(cnt[0])
+        assert n == len(want)
+        assert np.array_equal(oracle.sort_pairs(out[:n].cpu().numpy()), want)
+    t.free()
