@@ -283,6 +283,65 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     }
 
 
+def bench_batch_stream(A, torch, bws, batches: int = 200):
+    """A stream of batches over distinct instances: the batch workloads in
+    `bws` (each many tiny joins) alternate, one batch per call, first on one
+    stream, then on two streams with a workspace and outputs each, so that one
+    batch's kernels run beside the other's (no work is skipped or shared:
+    every batch signs, builds, probes and verifies all of its joins)."""
+    import numpy as np
+    dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
+    ins = []
+    for bw in bws:
+        R, S = A.DeviceKeys.from_host(bw.R), A.DeviceKeys.from_host(bw.S)
+        out, oseg, counts, _, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg)
+        ins.append((R, S, dev(bw.r_seg), dev(bw.s_seg), dev(oseg), out.shape[0], counts, bw))
+    J = bws[0].njoins
+    assert all(b.njoins == J for b in bws)
+    n_build = max(b.R.n for b in bws)
+    n_probe = max(b.S.n for b in bws)
+    cap = max(x[5] for x in ins)
+    lanes = []
+    for _ in range(2):
+        ws = torch.empty(A.asj_batch_workspace_bytes(J, n_build, n_probe), dtype=torch.uint8, device="cuda")
+        lanes.append((ws, torch.empty((cap, 2), dtype=torch.int32, device="cuda"),
+                      [torch.zeros(J, dtype=torch.int64, device="cuda") for _ in bws], torch.cuda.Stream()))
+    def run(k, lane, stream):
+        R, S, r_seg, s_seg, out_seg, _, _, _ = ins[k % len(ins)]
+        ws, out, cnts, _ = lanes[lane]
+        A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnts[k % len(ins)], None, None, workspace=ws,
+                         stream=stream)
+    def timed(two):
+        ran = set()
+        for k in range(8):  # warm-up, every lane and input
+            run(k, k % 2 if two else 0, lanes[k % 2][3] if two else None)
+        torch.cuda.synchronize()
+        for lane in lanes:
+            for c in lane[2]:
+                c.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(batches):
+            lane = k % 2 if two else 0
+            run(k, lane, lanes[k % 2][3] if two else None)
+            ran.add((lane, k % len(ins)))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / batches
+        for lane, i in ran:  # every (lane, input) that ran left the counts of that input's joins
+            assert (lanes[lane][2][i].cpu().numpy() == ins[i][6]).all(), "stream of batches changed the counts"
+        return ms
+    one = timed(False)
+    two = timed(True)
+    key_bytes = bws[0].R.nbytes + bws[0].S.nbytes
+    return {"joins_per_batch": J, "distinct_instances": J * len(bws), "batches": batches,
+            "key_bytes_per_batch": int(key_bytes),
+            "ms_per_batch_one_stream": round(one, 4), "ms_per_batch_two_streams": round(two, 4),
+            "key_gbps_two_streams": round(key_bytes / (two * 1e-3) / 1e9, 1),
+            "frac_peak_keys_two_streams": round(key_bytes / (two * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "note": "batches alternate between distinct instance sets (working set above the 256 MB Infinity "
+                    "Cache); two streams: consecutive batches overlap on the device"}
+
+
 def bench_tiny_latency(A, torch, W, runs: int = 1000):
     """Latency of one whole tiny join (R = S = 10k keys of 256 B): HIP events
     around each of `runs` calls (the inputs stay resident; the 6 MB of keys
@@ -632,6 +691,9 @@ def main():
         tw = tiny_instances(W, args.tiny_instances)
         tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup, autotune=not args.no_autotune)
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
+        tw2 = tiny_instances(W, args.tiny_instances, seed0=args.tiny_instances + 1)
+        tiny_batch["stream_of_batches"] = bench_batch_stream(A, torch, [tw, tw2], batches=max(50, 10 * args.steps))
+        del tw2
         log(f"tiny batch: {tiny_batch}")
 
     sweep = None
