@@ -176,3 +176,28 @@ def test_batch_invalid_segments_report_minus_one(A, wl, case):
     assert (counts == -1).all()
     _, _, counts, _, _ = A.join_batch(R, S, r_seg, s_seg)  # the same inputs with valid segments
     assert counts.tolist() == [1, 1, 1]
+
+
+@pytest.mark.parametrize("sig", [(16, 1), (8, 2), (8, 4)])
+@pytest.mark.parametrize("verify", [True, False])
+def test_batch_lds_tables_other_signatures(A, oracle, wl, sig, verify):
+    """Every signature width the batches offer, on LDS tables and on
+    device-memory tables, at several window sizes and grids: pairs and
+    candidate counts equal the oracle's signature join with the same
+    parameters (with verify=False, the paper-literal signature-equal pairs)."""
+    f, nsym = sig
+    parts = [wl.random_small(60 + s, m=200 + 150 * s, n=900 + 100 * s, max_len=[3, 12, 70, 200][s % 4],
+                             alphabet=b"abc\x00") for s in range(5)]
+    Rf, Sf, r_seg, s_seg = concat(wl, parts)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    flags = 0 if verify else A.ASJ_NO_VERIFY
+    wants = [oracle.join_signature(w.R, w.S, f=f, nsym=nsym, verify=verify) for w in parts]
+    for extra, kpw, rounds in ((0, 64, 1), (0, 16, 2), (A.ASJ_GLOBAL_TABLES, 32, 4)):
+        out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg, f=f, nsym=nsym, flags=flags | extra,
+                                                   keys_per_window=kpw, grid_rounds=rounds,
+                                                   caps=np.array([len(w[0]) + 16 for w in wants]))
+        outh = out.cpu().numpy()
+        for k, (want, want_cand) in enumerate(wants):
+            assert counts[k] == len(want), (extra, kpw, k)
+            assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want), (extra, kpw, k)
+            assert cands[k] == want_cand, (extra, kpw, k)
