@@ -134,6 +134,25 @@ __device__ __forceinline__ void asj_load_full(const uint8_t *__restrict__ data, 
     asj_align_full(r, kd);
 }
 
+// The first min(len, 16) bytes of the key at a, zero past them; reads only
+// 4-byte words that hold at least one of those bytes (none for len = 0).
+__device__ __forceinline__ void asj_load_head16(const uint8_t *__restrict__ data, int64_t a, int len, uint32_t k[4])
+{
+    const uint32_t sh = (uint32_t)(a & 3);
+    const uint32_t *p = (const uint32_t *)(data + (a - sh));
+    const int n = len < 16 ? len : 16;
+    const int avail = n + (int)sh; // bytes from p through the last wanted byte
+    uint32_t w[5];
+#pragma unroll
+    for (int t = 0; t < 5; t++) w[t] = (n > 0 && 4 * t < avail) ? p[t] : 0u;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const uint32_t v = __builtin_amdgcn_alignbyte(w[t + 1], w[t], sh);
+        const int keep = n - 4 * t;
+        k[t] = keep >= 4 ? v : keep <= 0 ? 0u : (v & ((1u << (8 * keep)) - 1u));
+    }
+}
+
 // Tail chunk: rem (1..63) key bytes at a; bytes at or past rem read as zero.
 __device__ __forceinline__ void asj_load_tail(const uint8_t *__restrict__ data, int64_t a, int rem, uint32_t kd[16])
 {

@@ -245,10 +245,8 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
 
     // the matching pairs themselves (every kind but the semi- and anti-join)
     const bool pairs_out = a.kind != ASJ_KIND_SEMI && a.kind != ASJ_KIND_ANTI;
-    // where the probe keys' and (for the plain join's first-chunk compare)
-    // the build keys' bytes end: short keys are read wide before these
+    // where the probe keys' bytes end: short keys are read wide before it
     const int64_t send = a.n > 0 ? a.soff[a.n] : 0;
-    const int64_t rend = (PLAIN && a.rn > 0) ? a.roff[a.rn] : 0;
     // What starts the next window -- its map entry (batch), or its keys'
     // offsets and ids (single join, LDS-table windows) -- is requested while
     // the current window is processed, so a window does not begin with a
@@ -354,23 +352,19 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 bool eq = has && lr == ls;
                 if (PLAIN && eq) {
                     // The plain table offers every occupied slot as a candidate, so
-                    // most equal-length pairs differ: each lane compares its pair's
-                    // first 64 bytes (or whole key) alone, and only pairs that agree
-                    // there go on to the chunk passes below.
-                    uint32_t kr[16], ks[16], diff = 0;
-                    if (ls >= ASJ_CHUNK) {
-                        asj_load_full(a.rdata, rs, kr);
-                        asj_load_full(a.sdata, ss, ks);
-                    } else {
-                        asj_load_tail_fast(a.rdata, rs, ls, rend, kr);
-                        asj_load_tail_fast(a.sdata, ss, ls, send, ks);
-                    }
+                    // equal-length pairs often differ: each lane compares its pair's
+                    // first 16 bytes alone, and only pairs that agree there go on to
+                    // the chunk passes below.  (Sixteen bytes: a 64-byte first chunk
+                    // held two raw chunks in registers and made the kernels spill.)
+                    uint32_t kr[4], ks[4], diff = 0;
+                    asj_load_head16(a.rdata, rs, ls, kr);
+                    asj_load_head16(a.sdata, ss, ls, ks);
 #pragma unroll
-                    for (int t = 0; t < 16; t++) diff |= kr[t] ^ ks[t];
+                    for (int t = 0; t < 4; t++) diff |= kr[t] ^ ks[t];
                     eq = diff == 0;
                 }
-                // the (remaining) chunks of every equal-length pair, one per lane
-                constexpr int kFirst = PLAIN ? 1 : 0; // chunks already compared
+                // every chunk of every equal-length pair, one per lane
+                constexpr int kFirst = 0; // chunks already compared
                 const int nch = eq ? max(0, (ls + ASJ_CHUNK - 1) / ASJ_CHUNK - kFirst) : 0;
                 const int incl = asj_wave_incl_scan(nch);
                 const int total = __shfl(incl, ASJ_WAVE - 1, ASJ_WAVE);
