@@ -283,7 +283,7 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     }
 
 
-def bench_batch_stream(A, torch, bws, batches: int = 200):
+def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 2):
     """A stream of batches over distinct instances: the batch workloads in
     `bws` (each many tiny joins) alternate, one batch per call, first on one
     stream, then on two streams with a workspace and outputs each, so that one
@@ -302,7 +302,7 @@ def bench_batch_stream(A, torch, bws, batches: int = 200):
     n_probe = max(b.S.n for b in bws)
     cap = max(x[5] for x in ins)
     lanes = []
-    for _ in range(2):
+    for _ in range(nlanes):
         ws = torch.empty(A.asj_batch_workspace_bytes(J, n_build, n_probe), dtype=torch.uint8, device="cuda")
         lanes.append((ws, torch.empty((cap, 2), dtype=torch.int32, device="cuda"),
                       [torch.zeros(J, dtype=torch.int64, device="cuda") for _ in bws], torch.cuda.Stream()))
@@ -314,7 +314,7 @@ def bench_batch_stream(A, torch, bws, batches: int = 200):
     def timed(two):
         ran = set()
         for k in range(8):  # warm-up, every lane and input
-            run(k, k % 2 if two else 0, lanes[k % 2][3] if two else None)
+            run(k, k % nlanes if two else 0, lanes[k % nlanes][3] if two else None)
         torch.cuda.synchronize()
         for lane in lanes:
             for c in lane[2]:
@@ -322,8 +322,8 @@ def bench_batch_stream(A, torch, bws, batches: int = 200):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(batches):
-            lane = k % 2 if two else 0
-            run(k, lane, lanes[k % 2][3] if two else None)
+            lane = k % nlanes if two else 0
+            run(k, lane, lanes[lane][3] if two else None)
             ran.add((lane, k % len(ins)))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / batches
