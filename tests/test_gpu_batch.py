@@ -201,3 +201,47 @@ def test_batch_lds_tables_other_signatures(A, oracle, wl, sig, verify):
             assert counts[k] == len(want), (extra, kpw, k)
             assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want), (extra, kpw, k)
             assert cands[k] == want_cand, (extra, kpw, k)
+
+
+@pytest.mark.parametrize("extra", [0, 0x400, 0x800])
+def test_batch_graph_replays_equal_eager(A, oracle, wl, extra):
+    """A batch call with a caller workspace, captured into a HIP graph and
+    replayed three times with eager work (another batch on other inputs, a
+    torch op) and synchronizations between the replays: every replay leaves
+    the eager call's counts and pairs (LDS tables, device-memory tables, and
+    the right outer join's unmatched-build kernel)."""
+    import torch
+    b = wl.batch(scale=0.003, njoins=12)
+    other = wl.batch(seed=9, scale=0.002, njoins=5)
+    R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
+    R2, S2 = A.DeviceKeys.from_host(other.R), A.DeviceKeys.from_host(other.S)
+    _, oseg, counts, _, _ = A.join_batch(R, S, b.r_seg, b.s_seg, flags=extra,
+                                         caps=np.diff(b.s_seg) + np.diff(b.r_seg) + 16)
+    J = b.njoins
+    dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
+    r_seg, s_seg, out_seg = dev(b.r_seg), dev(b.s_seg), dev(oseg)
+    ws = torch.empty(A.asj_batch_workspace_bytes(J, b.R.n, b.S.n, flags=extra), dtype=torch.uint8, device="cuda")
+    out = torch.full((int(oseg[-1]), 2), -7, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
+    call = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, None, workspace=ws, flags=extra)
+    call()
+    torch.cuda.synchronize()
+    eager_cnt = cnt.cpu().numpy().copy()
+    eager = [oracle.sort_pairs(out[oseg[k]:oseg[k] + eager_cnt[k]].cpu().numpy()) for k in range(J)]
+    assert (eager_cnt == counts).all()
+    st = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=st):
+        call()
+    for rep in range(3):
+        out.fill_(-7)
+        cnt.zero_()
+        A.join_batch(R2, S2, other.r_seg, other.s_seg)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        c = cnt.cpu().numpy()
+        assert (c == eager_cnt).all(), rep
+        for k in range(J):
+            assert np.array_equal(oracle.sort_pairs(out[oseg[k]:oseg[k] + c[k]].cpu().numpy()), eager[k]), (rep, k)
