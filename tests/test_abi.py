@@ -105,3 +105,15 @@ def test_host_join_checks_its_arguments_on_the_host(lib):
     o = _Opts(16, 2, 0.0, 0x10, 0, 0)
     assert f(P(R), P(R), P(o), None, out, ctypes.c_int64(4), P(cnt), None, None) == -6
     assert cnt.value == -7  # never written on a rejected call
+
+
+def test_header_constants_match_the_binding():
+    """Every #define ASJ_* value of the header (flags and status codes) is the
+    binding's constant of the same name."""
+    from paper_2411_18183_amd import asjoin as A
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(ASJ_[A-Z0-9_]+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", text, flags=re.M))
+    assert "ASJ_RIGHT_OUTER" in defs and "ASJ_GLOBAL_TABLES" in defs and "ASJ_EINVAL" in defs
+    for name, val in defs.items():
+        assert hasattr(A, name), name
+        assert getattr(A, name) == int(val, 0), name
