@@ -245,3 +245,26 @@ def test_batch_graph_replays_equal_eager(A, oracle, wl, extra):
         assert (c == eager_cnt).all(), rep
         for k in range(J):
             assert np.array_equal(oracle.sort_pairs(out[oseg[k]:oseg[k] + c[k]].cpu().numpy()), eager[k]), (rep, k)
+
+
+def test_batch_thousands_of_tiny_joins(A, oracle, wl):
+    """3000 joins of 0-6 rows each (more joins than one plan-kernel pass of
+    1024, many joins per block share, empty build and probe sides): every
+    join equals the oracle's, with LDS tables and with device-memory tables."""
+    rng = np.random.default_rng(77)
+    alphabet = [b"", b"a", b"b", b"ab", b"ba", b"abc"]
+    joins = []
+    for _ in range(3000):
+        m, n = int(rng.integers(0, 7)), int(rng.integers(0, 7))
+        joins.append(([alphabet[i] for i in rng.integers(0, len(alphabet), m)],
+                      [alphabet[i] for i in rng.integers(0, len(alphabet), n)]))
+    Rf, Sf, r_seg, s_seg = flatten(wl, joins)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    caps = np.array([max(1, len(a) * len(b)) for a, b in joins])
+    for extra in (0, A.ASJ_GLOBAL_TABLES):
+        out, oseg, counts, _, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=extra)
+        outh = out.cpu().numpy()
+        for k, (rk, sk) in enumerate(joins):
+            want = sorted((i, j) for j, s in enumerate(sk) for i, r in enumerate(rk) if r == s)
+            got = sorted(map(tuple, outh[oseg[k]:oseg[k] + counts[k]].tolist()))
+            assert counts[k] == len(want) and got == want, (extra, k)
