@@ -203,15 +203,16 @@ def test_batch_lds_tables_other_signatures(A, oracle, wl, sig, verify):
             assert cands[k] == want_cand, (extra, kpw, k)
 
 
+@pytest.mark.parametrize("njoins", [12, 40])
 @pytest.mark.parametrize("extra", [0, 0x400, 0x800])
-def test_batch_graph_replays_equal_eager(A, oracle, wl, extra):
+def test_batch_graph_replays_equal_eager(A, oracle, wl, extra, njoins):
     """A batch call with a caller workspace, captured into a HIP graph and
     replayed three times with eager work (another batch on other inputs, a
     torch op) and synchronizations between the replays: every replay leaves
     the eager call's counts and pairs (LDS tables, device-memory tables, and
     the right outer join's unmatched-build kernel)."""
     import torch
-    b = wl.batch(scale=0.003, njoins=12)
+    b = wl.batch(scale=0.003, njoins=njoins)
     other = wl.batch(seed=9, scale=0.002, njoins=5)
     R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
     R2, S2 = A.DeviceKeys.from_host(other.R), A.DeviceKeys.from_host(other.S)
