@@ -104,11 +104,13 @@ extern "C" {
                                 ASJ_PROBE_FUSED; both flags: ASJ_EINVAL.  The output is the
                                 same either way. */
 #define ASJ_GLOBAL_TABLES 0x400u /* asj_join_batch: every join's table is a segment of one
-                                device-memory slot array.  Without it, a join with at most
-                                10240 build rows gets no segment: each block that probes it
+                                device-memory slot array; asj_join: the table is built in
+                                device memory.  Without it, a join with at most 10240 build
+                                rows gets no device-memory table: each block that probes it
                                 builds the join's table in LDS from the build signatures
-                                (same candidates, same output set).  The split schedule
-                                always uses device-memory tables. */
+                                (same candidates, same output set).  The split schedule, the
+                                fingerprint control, 64-bit signatures and asj_build always
+                                use device-memory tables. */
 
 /* A relation's join attributes: key k is data[offsets[k] .. offsets[k+1]).
  * offsets must be non-decreasing (k = 0..n).  The library reads only

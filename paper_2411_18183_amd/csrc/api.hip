@@ -482,6 +482,115 @@ const uint16_t *asj_device_tables(int *dev)
     return g_dev[d].tab;
 }
 
+namespace {
+
+constexpr int kNotLocal = 1; // join_local_single: not this path
+
+// asj_join with at most ASJ_LOCAL_ROWS build rows: the build keys are signed
+// into a scratch array and every probing block builds the table in LDS (no
+// device-memory table, no insert).  Returns kNotLocal when the options ask
+// for a path it does not take (device-memory tables, the split schedule,
+// 64-bit signatures, the fingerprint control).
+int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+                      int64_t *out_count, int64_t *cand_count, hipStream_t st)
+{
+    if (!keys_ok(r) || r->n > ASJ_LOCAL_ROWS) return kNotLocal;
+    asj_opts o = {};
+    if (opts) o = *opts;
+    if (o.flags & (ASJ_GLOBAL_TABLES | ASJ_FINGERPRINT)) return kNotLocal;
+    const int plain = (o.flags & ASJ_PLAIN) != 0;
+    const int verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    if (plain && !verify) return kNotLocal; // the regular path reports the error
+    const int kind = join_kind(o.flags);
+    if (kind < 0) return kNotLocal;
+    asj_sig_params sig = {16, 2};
+    if (!plain && resolve_sig(o.sig, &sig) != ASJ_OK) return kNotLocal;
+    if (!plain && sig64(sig)) return kNotLocal;
+    float lf;
+    int kpw, split, rounds;
+    if (resolve_auto(0, r->n, o, &lf, &kpw, &split, &rounds) != ASJ_OK || split) return kNotLocal;
+    int dev = 0;
+    int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    const bool marks = asj_kind_marks_build(kind);
+    const int64_t rwords = marks ? (r->n + 3) / 4 : 0;
+    const size_t o_sig = 256, o_pst = align256(o_sig + 4 * (size_t)(r->n > 0 ? r->n : 1));
+    const size_t o_rm = align256(o_pst + 4), bytes = align256(o_rm + 4 * (size_t)(rwords > 0 ? rwords : 1));
+    uint8_t *blk = nullptr;
+    hipError_t e = hipMallocAsync((void **)&blk, bytes, st);
+    if (e != hipSuccess) return hip_fail(e);
+    int32_t *status = (int32_t *)blk;
+    uint32_t *sig_r = (uint32_t *)(blk + o_sig);
+    int32_t *pstatus = (int32_t *)(blk + o_pst);
+    uint8_t *rmatch = marks ? blk + o_rm : nullptr;
+    const int validate = (o.flags & ASJ_VALIDATE) != 0;
+    int out_rc = ASJ_OK;
+    do {
+        tim_begin("table_init", st);
+        e = asj_launch_local_init(out_count, cand_count, status, (uint32_t *)rmatch, rwords, st);
+        if (e == hipSuccess && validate) {
+            e = asj_launch_fill_i32(pstatus, 1, 0, st);
+            if (e == hipSuccess) e = asj_launch_validate(r->offsets, r->n, status, st);
+            if (e == hipSuccess && s->n > 0) e = asj_launch_validate(s->offsets, s->n, pstatus, st);
+        }
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        tim_begin(plain ? "hash_build" : "sign_build", st);
+        e = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, status);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        asj_probe_args a = {};
+        a.rdata = r->data;
+        a.roff = r->offsets;
+        a.rids = r->ids;
+        a.rn = r->n;
+        a.rsig = sig_r;
+        a.keys_per_window = kpw;
+        a.sdata = s->data;
+        a.soff = s->offsets;
+        a.sids = s->ids;
+        a.n = s->n;
+        a.out = out;
+        a.cap = out_cap;
+        a.out_count = out_count;
+        a.cand_count = cand_count;
+        a.table_status = status;
+        a.probe_status = validate ? pstatus : nullptr;
+        a.grid_rounds = rounds;
+        a.plain = plain;
+        a.verify = verify;
+        a.kind = kind;
+        a.rmatch = rmatch;
+        const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
+        // launched without probe keys too: it reports a failed validation
+        tim_begin(plain ? "hash_probe_verify" : "sign_probe_verify", st);
+        e = asj_launch_probe_local_single(&a, mode, plain ? 1 : sig.nsym, g_dev[dev].tab, st);
+        tim_end(st);
+        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        if (rmatch) {
+            tim_begin("unmatched_build", st);
+            e = asj_launch_unmatched_build(rmatch, r->ids, r->n, out, out_cap, out_count, status,
+                                           validate ? pstatus : nullptr, 0, nullptr, nullptr, st);
+            tim_end(st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        }
+        if ((o.flags & ASJ_SORTED) && out_cap > 0) {
+            void *scratch = nullptr;
+            e = hipMallocAsync(&scratch, asj_sort_scratch_bytes(out_cap), st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+            tim_begin("sort", st);
+            e = asj_launch_sort_pairs(out, out_count, out_cap, scratch, st);
+            tim_end(st);
+            (void)hipFreeAsync(scratch, st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        }
+    } while (0);
+    (void)hipFreeAsync(blk, st);
+    return out_rc;
+}
+
+} // namespace
+
 extern "C" {
 
 int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hipStream_t st)
@@ -519,6 +628,8 @@ int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pai
 {
     TimingScope ts;
     if (!keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
+    const int lrc = join_local_single(r, s, opts, out, out_cap, out_count, cand_count, st);
+    if (lrc != kNotLocal) return lrc;
     asj_table *t = nullptr;
     int rc = build_impl(r, opts, &t, st);
     if (rc != ASJ_OK) return rc;

@@ -454,6 +454,15 @@ struct asj_probe_args {
 // Signs the probe keys and probes/verifies/compacts in one kernel.
 hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab, int grid_cap,
                             hipStream_t st);
+// A single join whose a->rn <= ASJ_LOCAL_ROWS build rows have signatures
+// a->rsig: every probing block builds the LDS table itself (no device-memory
+// table); a->table_status must point to a cleared status word.
+hipError_t asj_launch_probe_local_single(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab,
+                                         hipStream_t st);
+// Clears the two counters (b may be NULL), sets *status = ASJ_OK and clears
+// words[0 .. nwords) (may be NULL), in one launch.
+hipError_t asj_launch_local_init(int64_t *a, int64_t *b, int32_t *status, uint32_t *words, int64_t nwords,
+                                 hipStream_t st);
 // Right and full outer joins: (r_id, -1) for every build row r < m with
 // rmatch[r] == 0, appended to the output like the probe kernel's pairs.
 // Batch (njoins > 0): row r belongs to join j with r_seg[j] <= r <

@@ -187,7 +187,10 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     int64_t nwin = BATCH ? min((int64_t)*a.nwin, a.nwin_cap) : (a.n + kpw - 1) / kpw;
     int64_t w_lo = 0, w_hi = 0, gblk = blockIdx.x, ngrid = gridDim.x;
     bool do_glob = true;
-    if (LOCAL) {
+    // a single join against an LDS table: every block builds the whole table
+    // (at most ASJ_LOCAL_ROWS build rows) and takes windows like a single join
+    constexpr bool kLocalSingle = LOCAL && !BATCH;
+    if (LOCAL && BATCH) {
         const int64_t nl = min((int64_t)*a.nwin_l, a.nwin_l_cap);
         const int64_t G = gridDim.x, b = blockIdx.x;
         int64_t gl = 0;
@@ -449,7 +452,59 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         }
     };
 
-    if (LOCAL) {
+    // The LDS table of build rows r0 .. r0 + nr (block-wide): their signatures
+    // read once into registers, bucket counts, their exclusive prefix sums,
+    // then every entry placed at its bucket's next position (which leaves
+    // lend[b] at the end of bucket b).
+    auto build_table = [&](int64_t r0, int nr) {
+        constexpr int kPer = (ASJ_LOCAL_ROWS + kBlock - 1) / kBlock;
+        uint32_t rsg[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int i = (int)threadIdx.x + q * kBlock;
+            rsg[q] = i < nr ? a.rsig[r0 + i] : 0u;
+        }
+        __syncthreads(); // the previous table's lookups are over
+        for (int b = threadIdx.x; b < kBuckets; b += kBlock) lend[b] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            if ((int)threadIdx.x + q * kBlock < nr) atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+        __syncthreads();
+        {
+            constexpr int per = kBuckets / kBlock; // consecutive buckets per thread
+            uint32_t c[per], sum = 0;
+#pragma unroll
+            for (int q = 0; q < per; q++) {
+                c[q] = lend[threadIdx.x * per + q];
+                sum += c[q];
+            }
+            const int incl = asj_wave_incl_scan((int)sum);
+            if (lane == ASJ_WAVE - 1) lwsum[wave] = (uint32_t)incl;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int q = 0; q < wave; q++) before += lwsum[q];
+            uint32_t run = before + (uint32_t)incl - sum;
+#pragma unroll
+            for (int q = 0; q < per; q++) {
+                lend[threadIdx.x * per + q] = run;
+                run += c[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int i = (int)threadIdx.x + q * kBlock;
+            if (i < nr) {
+                const uint32_t pos = atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+                if (!PLAIN) lsig[pos] = rsg[q];
+                lrow[pos] = (uint16_t)i;
+            }
+        }
+        __syncthreads();
+    };
+
+    if (LOCAL && BATCH) {
         // this block's share of the LDS-table windows, join by join
         for (int64_t w = w_lo; w < w_hi;) { // block-uniform
             const int j = __builtin_amdgcn_readfirstlane(a.win_l[w]);
@@ -462,55 +517,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
             // this wave's first window of the join
             pre_end = s1;
             if (w + wave < w_end) prefetch(s0 + (w + wave - wb) * kpw, true);
-            // the join's table: its signatures read once into registers, bucket
-            // counts, their exclusive prefix sums, then every entry placed at
-            // its bucket's next position (which leaves lend[b] at the end of
-            // bucket b)
-            constexpr int kPer = (ASJ_LOCAL_ROWS + kBlock - 1) / kBlock;
-            uint32_t rsg[kPer];
-#pragma unroll
-            for (int q = 0; q < kPer; q++) {
-                const int i = (int)threadIdx.x + q * kBlock;
-                rsg[q] = i < nr ? a.rsig[r0 + i] : 0u;
-            }
-            __syncthreads(); // the previous join's lookups are over
-            for (int b = threadIdx.x; b < kBuckets; b += kBlock) lend[b] = 0;
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < kPer; q++)
-                if ((int)threadIdx.x + q * kBlock < nr) atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
-            __syncthreads();
-            {
-                constexpr int per = kBuckets / kBlock; // consecutive buckets per thread
-                uint32_t c[per], sum = 0;
-#pragma unroll
-                for (int q = 0; q < per; q++) {
-                    c[q] = lend[threadIdx.x * per + q];
-                    sum += c[q];
-                }
-                const int incl = asj_wave_incl_scan((int)sum);
-                if (lane == ASJ_WAVE - 1) lwsum[wave] = (uint32_t)incl;
-                __syncthreads();
-                uint32_t before = 0;
-                for (int q = 0; q < wave; q++) before += lwsum[q];
-                uint32_t run = before + (uint32_t)incl - sum;
-#pragma unroll
-                for (int q = 0; q < per; q++) {
-                    lend[threadIdx.x * per + q] = run;
-                    run += c[q];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < kPer; q++) {
-                const int i = (int)threadIdx.x + q * kBlock;
-                if (i < nr) {
-                    const uint32_t pos = atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
-                    if (!PLAIN) lsig[pos] = rsg[q];
-                    lrow[pos] = (uint16_t)i;
-                }
-            }
-            __syncthreads();
+            build_table(r0, nr);
             stage_join = j;
             for (int64_t win = w + wave; win < w_end; win += kWaves) {
                 const int64_t k0 = s0 + (win - wb) * kpw;
@@ -523,8 +530,15 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     }
     if (do_glob) {
         const int64_t stride = ngrid * kWaves;
-        prefetch(gblk * kWaves + wave, false);
-        for (int64_t win = gblk * kWaves + wave; win < nwin; win += stride) {
+        const int64_t first = gblk * kWaves + wave;
+        if (kLocalSingle) { // the table, and the first window's rows (prefetch takes rows here)
+            pre_end = a.n;
+            prefetch(first < nwin ? first * kpw : -1, true);
+            build_table(0, (int)min((int64_t)ASJ_LOCAL_ROWS, a.rn));
+        } else {
+            prefetch(first, false);
+        }
+        for (int64_t win = first; win < nwin; win += stride) {
             // the window's rows, its join and table segment
             int64_t k0 = win * kpw;
             int rows = (int)min((int64_t)kpw, a.n - k0);
@@ -541,7 +555,10 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 mask = d.mask;
                 stage_join = j;
             }
-            window(j, k0, rows, slots, mask, 0, win + stride, false);
+            if (kLocalSingle)
+                window(0, k0, rows, nullptr, 0, 0, win + stride < nwin ? (win + stride) * kpw : -1, true);
+            else
+                window(j, k0, rows, slots, mask, 0, win + stride, false);
         }
     }
     flush();
@@ -712,6 +729,47 @@ hipError_t asj_launch_unmatched_build(const uint8_t *rmatch, const int32_t *rids
     hipLaunchKernelGGL(unmatched_build_kernel, dim3((unsigned)blocks), dim3(256), 0, st, rmatch, rids, m, out, cap,
                        out_count, status1, status2, njoins, r_seg, out_seg);
     return hipGetLastError();
+}
+
+// A single join against LDS tables: every block builds the whole table of
+// the a->rn <= ASJ_LOCAL_ROWS build rows from a->rsig, then takes every
+// grid-th window; grid_rounds x the resident blocks at most.
+template <int MODE, int NSYM, int PLAIN, int VERIFY>
+hipError_t launch_local_single(const asj_probe_args *a, const uint16_t *tab, hipStream_t st)
+{
+    constexpr int kBlock = Shape<0, 1>::block;
+    constexpr int kWaves = Shape<0, 1>::waves;
+    static const int64_t resident =
+        resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, 0, 1>), kBlock);
+    if (resident <= 0) return hipErrorInvalidValue;
+    const int64_t nwin = (a->n + a->keys_per_window - 1) / a->keys_per_window;
+    int64_t blocks = (nwin + kWaves - 1) / kWaves;
+    const int64_t most = resident * (a->grid_rounds > 0 ? a->grid_rounds : 1);
+    if (blocks > most) blocks = most;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, 0, 1>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                       st, *a, tab);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_probe_local_single(const asj_probe_args *a_in, int mode, int nsym, const uint16_t *tab,
+                                         hipStream_t st)
+{
+    asj_probe_args fixed = *a_in;
+    if (fixed.keys_per_window < 1 || fixed.keys_per_window > ASJ_WAVE) fixed.keys_per_window = ASJ_WAVE;
+    const asj_probe_args *a = &fixed;
+    if (!a->rsig || a->njoins != 0 || a->ssig || a->rn > ASJ_LOCAL_ROWS || !a->table_status)
+        return hipErrorInvalidValue;
+    if (a->plain) return launch_local_single<ASJ_MODE_PLAIN, 1, 1, 1>(a, tab, st);
+#define ASJ_LOCAL_SIG(M, N)                                                                                       \
+    if (mode == M && nsym == N)                                                                                   \
+        return a->verify ? launch_local_single<M, N, 0, 1>(a, tab, st) : launch_local_single<M, N, 0, 0>(a, tab, st);
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG16, 2)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG16, 1)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG8, 4)
+    ASJ_LOCAL_SIG(ASJ_MODE_SIG8, 2)
+#undef ASJ_LOCAL_SIG
+    return hipErrorInvalidValue;
 }
 
 hipError_t asj_launch_probe_local(const asj_probe_args *a_in, int mode, int nsym, const uint16_t *tab, hipStream_t st)

@@ -49,6 +49,21 @@ __global__ void zero2_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b)
     if (threadIdx.x == 1 && b) *b = 0;
 }
 
+// Counters, status word and a word array cleared in one launch (see
+// asj_launch_local_init).
+__global__ void local_init_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b, int32_t *__restrict__ status,
+                                  uint32_t *__restrict__ words, int64_t nwords)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+        *a = 0;
+        if (b) *b = 0;
+        *status = ASJ_OK;
+    }
+    if (words)
+        for (int64_t i = i0; i < nwords; i += (int64_t)gridDim.x * blockDim.x) words[i] = 0u;
+}
+
 __global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -115,6 +130,14 @@ hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, 
 {
     hipLaunchKernelGGL(table_init_kernel, dim3(grid_for(cap > 0 ? cap : 1, 256, 16384)), dim3(256), 0, st, slots, cap,
                        status);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_local_init(int64_t *a, int64_t *b, int32_t *status, uint32_t *words, int64_t nwords,
+                                 hipStream_t st)
+{
+    const int g = grid_for(nwords > 0 ? nwords : 1, 256, 4096);
+    hipLaunchKernelGGL(local_init_kernel, dim3(g), dim3(256), 0, st, a, b, status, words, nwords);
     return hipGetLastError();
 }
 

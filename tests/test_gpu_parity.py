@@ -28,11 +28,14 @@ def gpu_sigs(A, rel, f=16, nsym=2):
     return out.view(np.uint32).astype(np.uint64)
 
 
-SCHEDULES = ["split", "fused"]
+# fused: asj_join with at most 10240 build rows builds its table in LDS;
+# fused_global: the device-memory table for every size
+SCHEDULES = ["split", "fused", "fused_global"]
 
 
 def sched_flag(A, sched):
-    return {"split": A.ASJ_PROBE_SPLIT, "fused": A.ASJ_PROBE_FUSED}[sched]
+    return {"split": A.ASJ_PROBE_SPLIT, "fused": A.ASJ_PROBE_FUSED,
+            "fused_global": A.ASJ_PROBE_FUSED | A.ASJ_GLOBAL_TABLES}[sched]
 
 
 def gpu_join(A, R, S, sched=None, **kw):
