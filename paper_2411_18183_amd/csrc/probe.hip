@@ -133,6 +133,62 @@ __device__ __forceinline__ bool next_local(const uint32_t *lsig, const uint16_t 
     return false;
 }
 
+// The LDS table of build rows r0 .. r0 + nr (whole block; nr <=
+// ASJ_LOCAL_ROWS): their signatures rsig[..] read once into registers,
+// bucket counts, their exclusive prefix sums, then every entry placed at its
+// bucket's next position, which leaves lend[b] at the end of bucket b (the
+// bucket is the low bits of mix32(signature); lsig is unused for PLAIN).
+template <int kBlock, int kBuckets, int PLAIN>
+__device__ __forceinline__ void build_lds_table(const uint32_t *__restrict__ rsig, int64_t r0, int nr, uint32_t *lend,
+                                                uint32_t *lsig, uint16_t *lrow, uint32_t *lwsum, int lane, int wave)
+{
+    constexpr int kPer = (ASJ_LOCAL_ROWS + kBlock - 1) / kBlock;
+    uint32_t rsg[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {
+        const int i = (int)threadIdx.x + q * kBlock;
+        rsg[q] = i < nr ? rsig[r0 + i] : 0u;
+    }
+    __syncthreads(); // the previous table's lookups are over
+    for (int b = threadIdx.x; b < kBuckets; b += kBlock) lend[b] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; q++)
+        if ((int)threadIdx.x + q * kBlock < nr) atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+    __syncthreads();
+    {
+        constexpr int per = kBuckets / kBlock; // consecutive buckets per thread
+        uint32_t c[per], sum = 0;
+#pragma unroll
+        for (int q = 0; q < per; q++) {
+            c[q] = lend[threadIdx.x * per + q];
+            sum += c[q];
+        }
+        const int incl = asj_wave_incl_scan((int)sum);
+        if (lane == ASJ_WAVE - 1) lwsum[wave] = (uint32_t)incl;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int q = 0; q < wave; q++) before += lwsum[q];
+        uint32_t run = before + (uint32_t)incl - sum;
+#pragma unroll
+        for (int q = 0; q < per; q++) {
+            lend[threadIdx.x * per + q] = run;
+            run += c[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; q++) {
+        const int i = (int)threadIdx.x + q * kBlock;
+        if (i < nr) {
+            const uint32_t pos = atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
+            if (!PLAIN) lsig[pos] = rsg[q];
+            lrow[pos] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
 #pragma unroll
@@ -223,7 +279,9 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     int nstage = 0;     // staged pairs (wave-uniform)
     int stage_join = 0; // join of the current window (batch mode)
     // reserve output space for the staged pairs with one atomic and copy them out
-    auto flush = [&]() {
+    // (every lambda below is inlined at each use: a call would spill the
+    // kernel's registers)
+    auto flush = [&]() __attribute__((always_inline)) {
         if (nstage == 0) return;
         int64_t *cnt_p = a.out_count;
         asj_pair *out_p = a.out;
@@ -261,7 +319,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     int32_t pre_id = 0;
     int64_t pre_end = 0; // LDS-table windows: end of the current join's probe rows
     // w = the next window (lw, an LDS-table window: its first row, < 0 for none)
-    auto prefetch = [&](int64_t w, bool lw) {
+    auto prefetch = [&](int64_t w, bool lw) __attribute__((always_inline)) {
         if (LOCAL && lw) {
             const int64_t kk = w + lane;
             if (w >= 0 && lane < kpw && kk < pre_end) {
@@ -289,7 +347,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     // of the join, whose build rows start at row rbase; the next window's
     // prefetch is issued once this one's rows are read.
     auto window = [&](int j, int64_t k0, int rows, const uint64_t *slots, uint64_t mask, int64_t rbase,
-                      int64_t next, bool lw) {
+                      int64_t next, bool lw) __attribute__((always_inline)) {
         const int64_t k = k0 + lane;
         const bool valid = lane < rows && k >= 0 && k < a.n;
         int64_t ss = 0;
@@ -452,59 +510,8 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         }
     };
 
-    // The LDS table of build rows r0 .. r0 + nr (block-wide): their signatures
-    // read once into registers, bucket counts, their exclusive prefix sums,
-    // then every entry placed at its bucket's next position (which leaves
-    // lend[b] at the end of bucket b).
-    auto build_table = [&](int64_t r0, int nr) {
-        constexpr int kPer = (ASJ_LOCAL_ROWS + kBlock - 1) / kBlock;
-        uint32_t rsg[kPer];
-#pragma unroll
-        for (int q = 0; q < kPer; q++) {
-            const int i = (int)threadIdx.x + q * kBlock;
-            rsg[q] = i < nr ? a.rsig[r0 + i] : 0u;
-        }
-        __syncthreads(); // the previous table's lookups are over
-        for (int b = threadIdx.x; b < kBuckets; b += kBlock) lend[b] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kPer; q++)
-            if ((int)threadIdx.x + q * kBlock < nr) atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
-        __syncthreads();
-        {
-            constexpr int per = kBuckets / kBlock; // consecutive buckets per thread
-            uint32_t c[per], sum = 0;
-#pragma unroll
-            for (int q = 0; q < per; q++) {
-                c[q] = lend[threadIdx.x * per + q];
-                sum += c[q];
-            }
-            const int incl = asj_wave_incl_scan((int)sum);
-            if (lane == ASJ_WAVE - 1) lwsum[wave] = (uint32_t)incl;
-            __syncthreads();
-            uint32_t before = 0;
-            for (int q = 0; q < wave; q++) before += lwsum[q];
-            uint32_t run = before + (uint32_t)incl - sum;
-#pragma unroll
-            for (int q = 0; q < per; q++) {
-                lend[threadIdx.x * per + q] = run;
-                run += c[q];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kPer; q++) {
-            const int i = (int)threadIdx.x + q * kBlock;
-            if (i < nr) {
-                const uint32_t pos = atomicAdd(&lend[asj_mix32(rsg[q]) & (uint32_t)(kBuckets - 1)], 1u);
-                if (!PLAIN) lsig[pos] = rsg[q];
-                lrow[pos] = (uint16_t)i;
-            }
-        }
-        __syncthreads();
-    };
 
-    if (LOCAL && BATCH) {
+    if constexpr (LOCAL && BATCH) {
         // this block's share of the LDS-table windows, join by join
         for (int64_t w = w_lo; w < w_hi;) { // block-uniform
             const int j = __builtin_amdgcn_readfirstlane(a.win_l[w]);
@@ -517,7 +524,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
             // this wave's first window of the join
             pre_end = s1;
             if (w + wave < w_end) prefetch(s0 + (w + wave - wb) * kpw, true);
-            build_table(r0, nr);
+            build_lds_table<kBlock, kBuckets, PLAIN>(a.rsig, r0, nr, lend, lsig, lrow, lwsum, lane, wave);
             stage_join = j;
             for (int64_t win = w + wave; win < w_end; win += kWaves) {
                 const int64_t k0 = s0 + (win - wb) * kpw;
@@ -531,10 +538,11 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     if (do_glob) {
         const int64_t stride = ngrid * kWaves;
         const int64_t first = gblk * kWaves + wave;
-        if (kLocalSingle) { // the table, and the first window's rows (prefetch takes rows here)
+        if constexpr (kLocalSingle) { // the table, and the first window's rows (prefetch takes rows here)
             pre_end = a.n;
             prefetch(first < nwin ? first * kpw : -1, true);
-            build_table(0, (int)min((int64_t)ASJ_LOCAL_ROWS, a.rn));
+            build_lds_table<kBlock, kBuckets, PLAIN>(a.rsig, 0, (int)min((int64_t)ASJ_LOCAL_ROWS, a.rn), lend, lsig,
+                                                     lrow, lwsum, lane, wave);
         } else {
             prefetch(first, false);
         }
@@ -555,7 +563,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 mask = d.mask;
                 stage_join = j;
             }
-            if (kLocalSingle)
+            if constexpr (kLocalSingle)
                 window(0, k0, rows, nullptr, 0, 0, win + stride < nwin ? (win + stride) * kpw : -1, true);
             else
                 window(j, k0, rows, slots, mask, 0, win + stride, false);
