@@ -2,8 +2,9 @@
 times: asj_join with default options on the large single join (R = 1M,
 S = 4M keys, ~4.9 GB) and on the DNA join (R = 200k, S = 1M keys of
 1000-10000 bases), asj_join_batch over all 256 joins of the batched
-workload (~14 GB), and the continuous-batching server over the resident
-10M-key build side with requests of up to 1M keys.
+workload (~14 GB) and over 128 independent tiny joins (655 MB), and the
+continuous-batching server over the resident 10M-key build side with
+requests of up to 1M keys.
 
 Join outputs are compared with the oracle's hash join on the same inputs
 (exact multisets of integer pairs): whole joins where the oracle finishes
@@ -159,3 +160,37 @@ def test_full_size_host_join_partitioned_equals_oracle(A, oracle, wl):
     assert total == len(want) == expected
     assert np.array_equal(oracle.sort_pairs(got), want)
     A.asj_join_host_release()
+
+
+def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
+    """128 independent tiny joins (R = S = 10k keys of 256 B each, 655 MB) in
+    one batch, the benchmark's throughput configuration (every join's table
+    built in LDS; options left to the library): every join has exactly the
+    generator's 2000 matches, every output has the properties above, and a
+    seeded sample of whole joins equals the oracle pair for pair."""
+    parts = [wl.tiny(seed=1 + i) for i in range(128)]
+    def cat(rels):
+        lens = np.concatenate([r.lengths() for r in rels])
+        data = np.concatenate([r.data[:r.offsets[-1]] for r in rels] + [np.zeros(16, np.uint8)])
+        off = np.zeros(len(lens) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        return wl.Relation(data, off, np.concatenate([r.ids for r in rels]))
+    Rf, Sf = cat([p.R for p in parts]), cat([p.S for p in parts])
+    r_seg = np.concatenate([[0], np.cumsum([p.R.n for p in parts])]).astype(np.int64)
+    s_seg = np.concatenate([[0], np.cumsum([p.S.n for p in parts])]).astype(np.int64)
+    note(f"tiny instances: joins=128 R={Rf.n} S={Sf.n} bytes={Rf.nbytes + Sf.nbytes}")
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg)
+    assert (counts == 2000).all()
+    outh = out.cpu().numpy()
+    rng = np.random.default_rng(29)
+    for k, w in enumerate(parts):
+        p = outh[oseg[k]:oseg[k] + counts[k]]
+        assert ((p[:, 0] >= 0) & (p[:, 0] < w.R.n) & (p[:, 1] >= 0) & (p[:, 1] < w.S.n)).all(), k
+        assert unique_pairs(p), k
+        assert keys_equal(w.R, w.S, p, rng, count=100), k
+    for k in sorted(rng.choice(128, size=12, replace=False).tolist()):
+        want, want_cand = oracle.join_signature(parts[k].R, parts[k].S)
+        assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want), k
+        assert cands[k] == want_cand, k
+    note("tiny instances: 128 joins with 2000 pairs each; 12 sampled joins equal the oracle")
