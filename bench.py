@@ -283,12 +283,13 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     }
 
 
-def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 2):
+def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 4):
     """A stream of batches over distinct instances: the batch workloads in
     `bws` (each many tiny joins) alternate, one batch per call, first on one
-    stream, then on two streams with a workspace and outputs each, so that one
-    batch's kernels run beside the other's (no work is skipped or shared:
-    every batch signs, builds, probes and verifies all of its joins)."""
+    stream, then round-robin over `nlanes` streams with a workspace and
+    outputs each, so that consecutive batches' kernels run beside each other
+    (no work is skipped or shared: every batch signs, builds, probes and
+    verifies all of its joins)."""
     import numpy as np
     dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
     ins = []
@@ -311,10 +312,10 @@ def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 2):
         ws, out, cnts, _ = lanes[lane]
         A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnts[k % len(ins)], None, None, workspace=ws,
                          stream=stream)
-    def timed(two):
+    def timed(multi):
         ran = set()
         for k in range(8):  # warm-up, every lane and input
-            run(k, k % nlanes if two else 0, lanes[k % nlanes][3] if two else None)
+            run(k, k % nlanes if multi else 0, lanes[k % nlanes][3] if multi else None)
         torch.cuda.synchronize()
         for lane in lanes:
             for c in lane[2]:
@@ -322,8 +323,8 @@ def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(batches):
-            lane = k % nlanes if two else 0
-            run(k, lane, lanes[lane][3] if two else None)
+            lane = k % nlanes if multi else 0
+            run(k, lane, lanes[lane][3] if multi else None)
             ran.add((lane, k % len(ins)))
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / batches
@@ -331,15 +332,16 @@ def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 2):
             assert (lanes[lane][2][i].cpu().numpy() == ins[i][6]).all(), "stream of batches changed the counts"
         return ms
     one = timed(False)
-    two = timed(True)
+    multi = timed(True)
     key_bytes = bws[0].R.nbytes + bws[0].S.nbytes
     return {"joins_per_batch": J, "distinct_instances": J * len(bws), "batches": batches,
-            "key_bytes_per_batch": int(key_bytes),
-            "ms_per_batch_one_stream": round(one, 4), "ms_per_batch_two_streams": round(two, 4),
-            "key_gbps_two_streams": round(key_bytes / (two * 1e-3) / 1e9, 1),
-            "frac_peak_keys_two_streams": round(key_bytes / (two * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "key_bytes_per_batch": int(key_bytes), "streams": nlanes,
+            "ms_per_batch_one_stream": round(one, 4), "ms_per_batch_multi_stream": round(multi, 4),
+            "key_gbps_multi_stream": round(key_bytes / (multi * 1e-3) / 1e9, 1),
+            "frac_peak_keys_multi_stream": round(key_bytes / (multi * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "note": "batches alternate between distinct instance sets (working set above the 256 MB Infinity "
-                    "Cache); two streams: consecutive batches overlap on the device"}
+                    "Cache); multi-stream: consecutive batches round-robin over the streams and overlap on the "
+                    "device"}
 
 
 def bench_tiny_latency(A, torch, W, runs: int = 1000):
@@ -692,7 +694,7 @@ def main():
         tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup, autotune=not args.no_autotune)
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
         tw2 = tiny_instances(W, args.tiny_instances, seed0=args.tiny_instances + 1)
-        tiny_batch["stream_of_batches"] = bench_batch_stream(A, torch, [tw, tw2], batches=max(50, 10 * args.steps))
+        tiny_batch["stream_of_batches"] = bench_batch_stream(A, torch, [tw, tw2], batches=max(200, 10 * args.steps))
         del tw2
         log(f"tiny batch: {tiny_batch}")
 
