@@ -34,11 +34,13 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
                                                                 uint64_t *__restrict__ tot, int32_t *__restrict__ status)
 {
     constexpr int Q = 4; // scanned quantities
-    __shared__ uint64_t scan[Q][kPlanBlock];
+    constexpr int kWaves = kPlanBlock / ASJ_WAVE;
+    __shared__ uint64_t wtot[Q][kWaves]; // per-wave totals of the current pass
     __shared__ uint64_t carry[Q];
     __shared__ int bad;
     const uint64_t start = wall_clock64();
     const int tid = threadIdx.x;
+    const int lane = tid % ASJ_WAVE, wave = tid / ASJ_WAVE;
     if (tid < Q) carry[tid] = 0;
     if (tid == 0) bad = (r_seg[0] != 0 || s_seg[0] != 0 || r_seg[J] != n_r || s_seg[J] != n_s);
     __syncthreads();
@@ -60,31 +62,41 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
                 v[2] = nw;
             }
         }
+        // inclusive scans: within each wave by shuffles, then over the
+        // waves' totals
+        uint64_t inc[Q];
 #pragma unroll
-        for (int q = 0; q < Q; q++) scan[q][tid] = v[q];
-        __syncthreads();
-        for (int d = 1; d < kPlanBlock; d <<= 1) { // inclusive scans
-            uint64_t add[Q];
+        for (int q = 0; q < Q; q++) {
+            uint64_t x = v[q];
 #pragma unroll
-            for (int q = 0; q < Q; q++) add[q] = tid >= d ? scan[q][tid - d] : 0;
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < Q; q++) scan[q][tid] += add[q];
-            __syncthreads();
+            for (int d = 1; d < ASJ_WAVE; d <<= 1) {
+                const uint64_t y = __shfl_up(x, d, ASJ_WAVE);
+                if (lane >= d) x += y;
+            }
+            inc[q] = x;
+            if (lane == ASJ_WAVE - 1) wtot[q][wave] = x;
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; q++)
+            for (int w = 0; w < wave; w++) inc[q] += wtot[q][w];
         if (j < J) {
-            desc[j].tbase = carry[0] + scan[0][tid] - v[0];
+            desc[j].tbase = carry[0] + inc[0] - v[0];
             desc[j].mask = v[0] - 1; // ~0 for an LDS table
-            desc[j].wbase_r = (int64_t)(carry[1] + scan[1][tid] - v[1]);
-            desc[j].wbase = (int64_t)(carry[2] + scan[2][tid] - v[2]);
-            desc[j].wbase_l = (int64_t)(carry[3] + scan[3][tid] - v[3]);
+            desc[j].wbase_r = (int64_t)(carry[1] + inc[1] - v[1]);
+            desc[j].wbase = (int64_t)(carry[2] + inc[2] - v[2]);
+            desc[j].wbase_l = (int64_t)(carry[3] + inc[3] - v[3]);
             rows_done[j] = 0;
             out_count[j] = 0;
             if (cand_count) cand_count[j] = 0;
             if (done_clock) done_clock[j] = (s_seg[j + 1] <= s_seg[j]) ? start : 0;
         }
-        __syncthreads();
-        if (tid < Q) carry[tid] += scan[tid][kPlanBlock - 1];
+        __syncthreads(); // every thread has read carry and the wave totals
+        if (tid < Q) {
+            uint64_t t = 0;
+            for (int w = 0; w < kWaves; w++) t += wtot[tid][w];
+            carry[tid] += t;
+        }
         __syncthreads();
     }
     if (tid < Q) tot[tid] = bad ? 0 : carry[tid];
