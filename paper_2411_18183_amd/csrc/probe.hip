@@ -28,7 +28,7 @@
 //      cost 11% of the kernel.
 // The baseline simple hash join runs the same kernel with the plain key hash
 // and treats every occupied slot as a candidate (no signature stored); its
-// byte comparison stops after the first 64 bytes when they differ.
+// byte comparison stops after the first 16 bytes when they differ.
 // In batch mode windows never span two joins: a window reads its join from
 // the window map, probes that join's table segment, appends to that join's
 // output segment, and the wave that finishes a join's last probe row stamps
@@ -40,7 +40,11 @@
 // for every join in its share, first builds the join's table in LDS from the
 // build signatures (a bucket per value of the low bits of mix32(signature),
 // entries ordered by bucket with a counting sort), so a walk is a few LDS
-// reads and no device-memory table is written, initialised or read.
+// reads and no device-memory table is written, initialised or read.  A
+// single join with few build rows runs the LOCAL form too: every block
+// builds the whole table, then takes every grid-th window.
+// Right and full outer joins: every verified match marks its build row in a
+// byte array, and unmatched_build_kernel appends the unmarked rows.
 #include "sign_window.h"
 
 namespace {
