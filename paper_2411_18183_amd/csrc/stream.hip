@@ -405,13 +405,17 @@ hipError_t sign_rel(Ctx &c, const DevRel &d, int64_t n, hipStream_t st)
 
 // ---- partitioning pass ----
 // Two lanes (stream + buffers) take alternate chunks, so that one chunk's
-// grouped output goes back to the host while the next chunk comes in.
+// grouped output goes back to the host while the next chunk comes in.  A
+// chunk's host-to-device copies start once the previous chunk's have ended
+// (in_done), so the two directions of the host link overlap instead of two
+// chunks sharing one direction.
 struct Lane {
     DevRel in, grp;
     int64_t *dpos = nullptr, *info = nullptr;
     unsigned long long *cnt = nullptr, *cursor = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t in_done = nullptr; // the chunk's input is on the device
     bool busy = false;
 };
 
@@ -426,6 +430,7 @@ int open_lane(Ctx &c, Lane &l, int64_t mk, int64_t mb, int P, hipEvent_t after)
     if (rc != ASJ_OK) return rc;
     hipError_t e = hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&l.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&l.in_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamWaitEvent(l.st, after, 0);
     return from_hip(e);
 }
@@ -440,19 +445,27 @@ void close_lane(Ctx &c, Lane &l, int64_t mk, int P)
     dfree(c, l.cursor, 8 * (size_t)P);
     dfree(c, l.info, 32 * (size_t)P);
     if (l.ev) (void)hipEventDestroy(l.ev);
+    if (l.in_done) (void)hipEventDestroy(l.in_done);
     if (l.st) (void)hipStreamDestroy(l.st);
     l = Lane();
 }
 
 // Signs and groups rows [a, b) of h on lane l and copies the grouped chunk
-// into hc's pinned region; completion is l.ev.
-int partition_chunk(Ctx &c, Lane &l, const HostRel &h, int64_t a, int64_t b, int logp, HostChunk &hc)
+// into hc's pinned region; completion is l.ev.  The input copies wait for
+// prev_in (the previous chunk's input copies, may be NULL).
+int partition_chunk(Ctx &c, Lane &l, const HostRel &h, int64_t a, int64_t b, int logp, HostChunk &hc,
+                    hipEvent_t prev_in)
 {
     const int P = 1 << logp;
     const int64_t nk = b - a, nb = rows_bytes(h, a, b);
+    if (prev_in) {
+        const int rw = from_hip(hipStreamWaitEvent(l.st, prev_in, 0));
+        if (rw != ASJ_OK) return rw;
+    }
     int rc = load_rows(c, h, a, b, l.in, 0, 0, l.st);
     if (rc != ASJ_OK) return rc;
-    hipError_t e = sign_rel(c, l.in, nk, l.st);
+    hipError_t e = hipEventRecord(l.in_done, l.st);
+    if (e == hipSuccess) e = sign_rel(c, l.in, nk, l.st);
     if (e == hipSuccess) e = asj_launch_fill_i64((int64_t *)l.cnt, P, 0, l.st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(part_hist_kernel, dim3(grid_for(nk, 256)), dim3(256), 0, l.st, l.in.sig, l.in.off, nk, logp,
@@ -526,7 +539,9 @@ int partition_rel(Ctx &c, const HostRel &h, int logp, HostStore &store, int whic
     for (size_t i = 0; rc == ASJ_OK && i < ranges.size(); i++) {
         Lane &l = lanes[i & 1];
         rc = lane_wait(l);
-        if (rc == ASJ_OK) rc = partition_chunk(c, l, h, ranges[i].a, ranges[i].b, logp, store.chunks[i]);
+        if (rc == ASJ_OK)
+            rc = partition_chunk(c, l, h, ranges[i].a, ranges[i].b, logp, store.chunks[i],
+                                 i > 0 ? lanes[(i - 1) & 1].in_done : nullptr);
     }
     for (int i = 0; i < 2; i++) {
         const int r2 = lane_wait(lanes[i]);
