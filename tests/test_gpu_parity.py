@@ -566,3 +566,23 @@ def test_right_outer_probe_calls_report_their_own_unmatched_rows(A, oracle, wl):
         assert n == len(want)
         assert np.array_equal(oracle.sort_pairs(out[:n].cpu().numpy()), want)
     t.free()
+
+
+@pytest.mark.parametrize("m", [10239, 10240, 10241])
+def test_single_join_at_the_lds_table_limit(A, oracle, wl, m):
+    """asj_join with one build row below, at and above the LDS-table limit
+    (10240 rows: a table built in LDS by every probing block; 10241: the
+    device-memory table): inner join with candidate counts, and the outer
+    kinds whose unmatched build rows come from the per-row match marks,
+    with caller ids on both sides."""
+    w = wl.random_small(m, m=m, n=12000, alphabet=bytes(range(256)), lengths=[3, 8, 16, 33, 64, 130])
+    w.R.ids = (np.random.default_rng(m).permutation(w.R.n) + 500).astype(np.int32)
+    w.S.ids = (np.random.default_rng(m + 1).permutation(w.S.n) + 90000).astype(np.int32)
+    want, want_cand = oracle.join_signature(w.R, w.S)
+    got, total, ncand = gpu_join(A, w.R, w.S)
+    assert total == len(want) and ncand == want_cand
+    assert np.array_equal(oracle.sort_pairs(got), want)
+    for kind in ("left", "right", "full"):
+        got, total, _ = gpu_join(A, w.R, w.S, flags=KINDS[kind])
+        want = oracle.join_variant(w.R, w.S, kind)
+        assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), kind
