@@ -109,6 +109,37 @@ def test_batch_lds_tables_beside_device_tables(A, oracle, wl, kind, plain):
         assert np.array_equal(oracle.sort_pairs(refh[rseg[k]:rseg[k] + rcounts[k]]), mine), (kind, plain, k)
 
 
+@pytest.mark.parametrize("extra", [0, 0x400])
+@pytest.mark.parametrize("kind", [k for k in sorted(KINDS) if k != "inner"])
+def test_batch_kinds_with_empty_sides(A, oracle, wl, kind, extra):
+    """Semi, anti and outer joins in a batch that opens and ends with empty
+    joins and mixes empty build sides, empty probe sides, both empty and a
+    join above the LDS-table limit: the rows without a partner (build rows
+    found through the segment bounds) go to their own join's output."""
+    big_r = [b"%07d" % i for i in range(10300)]
+    big_s = [b"%07d" % (3 * i) for i in range(5000)] + [b"q%d" % i for i in range(700)]
+    joins = [
+        ([], []),
+        ([], [b"a", b"b", b"a"]),
+        ([b"a", b"b", b"b"], []),
+        ([], []),
+        ([b"k" * 40] * 3 + [b"", b"z"], [b"k" * 40, b"", b"", b"y"]),
+        (big_r, big_s),
+        ([b"a"], []),
+        ([], [b"a"]),
+        ([], []),
+    ]
+    Rf, Sf, r_seg, s_seg = flatten(wl, joins)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    caps = np.array([len(a) + len(b) + 16 for a, b in joins])
+    got, oseg, counts, _, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=KINDS[kind] | extra)
+    goth = got.cpu().numpy()
+    for k, (rk, sk) in enumerate(joins):
+        want = oracle.join_variant(wl.from_keys(rk), wl.from_keys(sk), kind)
+        mine = oracle.sort_pairs(goth[oseg[k]:oseg[k] + counts[k]])
+        assert counts[k] == len(want) and np.array_equal(mine, want), (kind, extra, k)
+
+
 def test_batch_empty_joins_duplicates_and_caller_workspace(A, oracle, wl):
     import torch
     joins = [
