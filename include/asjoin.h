@@ -431,7 +431,10 @@ int asj_server_submit(asj_server *s, const uint8_t *data, const int64_t *offsets
                       int64_t out_cap, int64_t *ticket);
 
 /* Blocks until the request has finished; fills info (may be NULL), releases
- * the ticket and returns the request's status. */
+ * the ticket and returns the request's status.  One waiter per ticket: a
+ * second call for a ticket that another thread already waits on, or for a
+ * released or unknown ticket, returns ASJ_EINVAL at once.  Waits must not
+ * overlap asj_server_destroy. */
 int asj_server_wait(asj_server *s, int64_t ticket, asj_request_info *info);
 
 int asj_server_stats(asj_server *s, asj_server_stats_t *stats);

@@ -142,6 +142,25 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _need_dev(t, dtype, numel, what):
+    """Raise ValueError unless t is a contiguous device tensor of dtype with at
+    least numel elements (the library writes through its pointer)."""
+    if t is None or not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: a device tensor is required")
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what}: must be a contiguous cuda {dtype} tensor")
+    if t.numel() < numel:
+        raise ValueError(f"{what}: holds {t.numel()} elements, needs at least {numel}")
+
+
+def _need_pairs(out, what):
+    """out must be a contiguous cuda int32 tensor of shape [cap, 2]; returns cap."""
+    if out is None or not isinstance(out, torch.Tensor) or out.dim() != 2 or out.shape[1] != 2:
+        raise ValueError(f"{what}: must be an int32 tensor of shape [cap, 2]")
+    _need_dev(out, torch.int32, 0, what)
+    return out.shape[0]
+
+
 @dataclass
 class DeviceKeys:
     """A relation's join attributes in device memory (see asj_keys)."""
@@ -176,9 +195,11 @@ def asj_signature(keys: DeviceKeys, f: int = 16, nsym: int = 2, out: Optional[to
                   stream=None) -> torch.Tensor:
     """Signatures of every key (int32 tensor holding the uint32 bit patterns;
     2 words per key, the low word first, for 64-bit signatures f * nsym = 64)."""
+    words = 2 if f * nsym == 64 else 1
     if out is None:
-        words = 2 if f * nsym == 64 else 1
         out = torch.empty(max(keys.n, 0) * words, dtype=torch.int32, device=keys.offsets.device)
+    else:
+        _need_dev(out, torch.int32, keys.n * words, "asj_signature out")
     k = keys.c()
     _check(lib().asj_signature(ctypes.byref(k), asj_sig_params(f, nsym),
                                ctypes.c_void_p(out.data_ptr() if out.numel() else None), _stream(stream)),
@@ -228,7 +249,8 @@ def asj_build(R: DeviceKeys, f: int = 16, nsym: int = 2, load_factor: float = 0.
 def asj_probe(t: Table, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, stream=None):
     """Launch the probe.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
     k = S.c()
-    cap = out.shape[0]
+    cap = _need_pairs(out, "asj_probe out")
+    _need_dev(counts, torch.int64, 2, "asj_probe counts")
     _check(lib().asj_probe(t.handle, ctypes.byref(k), ctypes.c_void_p(out.data_ptr() if cap else None), cap,
                            ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(counts.data_ptr() + 8),
                            _stream(stream)), "asj_probe")
@@ -239,7 +261,8 @@ def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tens
     """Launch a whole join.  out: int32 [cap, 2]; counts: int64 [2] -> (|T|, candidates)."""
     kr, ks = R.c(), S.c()
     o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
-    cap = out.shape[0]
+    cap = _need_pairs(out, "asj_join out")
+    _need_dev(counts, torch.int64, 2, "asj_join counts")
     _check(lib().asj_join(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
                           ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.c_void_p(counts.data_ptr()),
                           ctypes.c_void_p(counts.data_ptr() + 8), _stream(stream)), "asj_join")
@@ -332,6 +355,9 @@ def timing_read(cap: int = 16):
 
 
 def asj_util_read(src: torch.Tensor, nbytes: int, out_word: torch.Tensor, grid: int = 0, stream=None):
+    _need_dev(out_word, torch.int32, 1, "asj_util_read out_word")
+    if not src.is_cuda or not src.is_contiguous() or nbytes < 0 or nbytes > src.numel() * src.element_size():
+        raise ValueError("asj_util_read: src must be a contiguous cuda tensor of at least nbytes bytes")
     L = lib()
     L.asj_util_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     L.asj_util_read.restype = ctypes.c_int
@@ -340,6 +366,9 @@ def asj_util_read(src: torch.Tensor, nbytes: int, out_word: torch.Tensor, grid: 
 
 
 def asj_util_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, stream=None):
+    for t, what in ((dst, "dst"), (src, "src")):
+        if not t.is_cuda or not t.is_contiguous() or nbytes < 0 or nbytes > t.numel() * t.element_size():
+            raise ValueError(f"asj_util_copy: {what} must be a contiguous cuda tensor of at least nbytes bytes")
     _check(lib().asj_util_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes),
                                _stream(stream)), "asj_util_copy")
 
@@ -372,6 +401,16 @@ def asj_join_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: tor
     for t in (r_seg, s_seg, out_seg, out_count, cand_count, done_clock):
         if t is not None and (not t.is_cuda or t.dtype != torch.int64 or not t.is_contiguous()):
             raise ValueError("batch: segment, count and clock tensors must be contiguous cuda int64")
+    if J < 1 or s_seg.numel() != J + 1 or out_seg.numel() != J + 1:
+        raise ValueError("batch: r_seg, s_seg and out_seg must each hold njoins + 1 entries")
+    _need_dev(out_count, torch.int64, J, "batch out_count")
+    if cand_count is not None:
+        _need_dev(cand_count, torch.int64, J, "batch cand_count")
+    if done_clock is not None:
+        _need_dev(done_clock, torch.int64, J + 1, "batch done_clock")
+    _need_pairs(out, "batch out")  # out_seg (read on the device) must stay within out.shape[0]
+    if workspace is not None:
+        _need_dev(workspace, torch.uint8, 0, "batch workspace")
     b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count),
                   _ptr(cand_count), _ptr(done_clock), _ptr(workspace),
                   int(workspace.numel()) if workspace is not None else 0)
@@ -391,6 +430,8 @@ def autotune(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, out_count: torch.T
              flags: int = 0, stream=None) -> dict:
     """Run the library's autotuner on these relations (see asj_autotune); later calls that leave the load
     factor, keys per window, grid rounds and schedule at 0 use its choice."""
+    _need_pairs(out, "autotune out")
+    _need_dev(out_count, torch.int64, 1, "autotune out_count")
     rk, sk = R.c(), S.c()
     o = _opts(f, nsym, 0.0, flags)
     res = asj_tune_result()
@@ -403,6 +444,10 @@ def autotune_batch(R: DeviceKeys, S: DeviceKeys, r_seg: torch.Tensor, s_seg: tor
                    out_seg: torch.Tensor, out_count: torch.Tensor, f: int = 16, nsym: int = 2, flags: int = 0,
                    stream=None) -> dict:
     J = r_seg.numel() - 1
+    for t, what in ((r_seg, "r_seg"), (s_seg, "s_seg"), (out_seg, "out_seg")):
+        _need_dev(t, torch.int64, J + 1, f"autotune_batch {what}")
+    _need_dev(out_count, torch.int64, J, "autotune_batch out_count")
+    _need_pairs(out, "autotune_batch out")
     b = asj_batch(R.c(), S.c(), _ptr(r_seg), _ptr(s_seg), J, _ptr(out), _ptr(out_seg), _ptr(out_count), None,
                   None, None, 0)
     o = _opts(f, nsym, 0.0, flags)
@@ -517,8 +562,19 @@ class Server:
 
     def submit(self, data, offsets, out, out_cap: Optional[int] = None) -> int:
         """Queue a request; data uint8 / offsets int64 / out int32 [cap, 2] host buffers kept alive until wait()."""
+        def dtype_of(a):
+            return a.dtype if isinstance(a, torch.Tensor) else torch.from_numpy(a[:0]).dtype
+        if dtype_of(offsets) != torch.int64 or (data is not None and dtype_of(data) != torch.uint8):
+            raise ValueError("server request: data must be uint8 and offsets int64")
         n = (offsets.numel() if isinstance(offsets, torch.Tensor) else offsets.size) - 1
-        cap = (out.shape[0] if out is not None else 0) if out_cap is None else out_cap
+        rows = 0
+        if out is not None:
+            if dtype_of(out) != torch.int32 or len(out.shape) != 2 or out.shape[1] != 2:
+                raise ValueError("server request: out must be an int32 buffer of shape [cap, 2]")
+            rows = out.shape[0]
+        cap = rows if out_cap is None else int(out_cap)
+        if cap < 0 or cap > rows:
+            raise ValueError(f"server request: out_cap {cap} exceeds the {rows} rows of out")
         t = ctypes.c_int64()
         _check(_server_lib().asj_server_submit(self.handle, _host_ptr(data), _host_ptr(offsets), n, _host_ptr(out),
                                                int(cap), ctypes.byref(t)), "asj_server_submit")
@@ -528,7 +584,8 @@ class Server:
     def wait(self, ticket: int) -> dict:
         info = asj_request_info()
         rc = _server_lib().asj_server_wait(self.handle, int(ticket), ctypes.byref(info))
-        self._live.pop(ticket, None)
+        if rc != ASJ_EINVAL:  # EINVAL: another caller waits on the ticket and still needs its buffers
+            self._live.pop(ticket, None)
         return {"status": rc, "count": int(info.count), "t_arrive_ms": info.t_arrive_ms,
                 "t_launch_ms": info.t_launch_ms, "t_done_ms": info.t_done_ms, "batch_id": info.batch_id,
                 "batch_requests": info.batch_requests}

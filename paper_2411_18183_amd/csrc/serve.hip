@@ -45,6 +45,7 @@ struct Req {
     int64_t count = 0;
     int status = ASJ_OK;
     bool done = false;
+    bool claimed = false; // a caller waits on this ticket (one waiter per ticket)
     int batch_id = -1, batch_n = 0;
 };
 
@@ -455,8 +456,9 @@ int asj_server_wait(asj_server *S, int64_t ticket, asj_request_info *info)
     if (!S) return ASJ_EINVAL;
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return ASJ_EINVAL;
+    if (it == S->reqs.end() || it->second->claimed) return ASJ_EINVAL; // unknown, or another caller waits on it
     Req *r = it->second;
+    r->claimed = true; // the only waiter: it alone erases and deletes the request
     S->cv_done.wait(lk, [r] { return r->done; });
     if (info) {
         info->status = r->status;
@@ -468,7 +470,7 @@ int asj_server_wait(asj_server *S, int64_t ticket, asj_request_info *info)
         info->batch_requests = r->batch_n;
     }
     const int st = r->status;
-    S->reqs.erase(it);
+    S->reqs.erase(ticket);
     delete r;
     return st;
 }

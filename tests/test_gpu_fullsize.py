@@ -1,18 +1,24 @@
 """Parity at full workload sizes, in the launch configurations the benchmark
-times: asj_join with default options on the large single join (R = 1M,
-S = 4M keys, ~4.9 GB) and on the DNA join (R = 200k, S = 1M keys of
-1000-10000 bases), asj_join_batch over all 256 joins of the batched
-workload (~14 GB) and over 128 independent tiny joins (655 MB), and the
-continuous-batching server over the resident 10M-key build side with
-requests of up to 1M keys.
+times.
 
-Join outputs are compared with the oracle's hash join on the same inputs
-(exact multisets of integer pairs): whole joins where the oracle finishes
-in about 20 s (large, DNA, every served request), a seeded sample of whole
-joins for the batched workload.  Signatures of sampled keys are compared
-bit for bit.  On every output, properties that hold at any size are
-checked as well: no pair twice, ids inside their join, and the keys of
-sampled emitted pairs byte-equal.
+* The large single join (R = 1M, S = 4M keys, ~4.9 GB) and the DNA join
+  (R = 200k, S = 1M keys of 1000-10000 bases) through asj_join: with the
+  library defaults, with the autotuner's choice (what the benchmark times:
+  options left to the library after asj_autotune on the same inputs), and
+  with every probe configuration the autotuner may choose on the
+  device-memory table (load factor, keys per window, grid rounds, probe
+  schedule).  Every output is compared pair for pair with one oracle
+  signature join, candidate count included.
+* asj_join_batch over all 256 joins of the batched workload (~14 GB): every
+  join compared pair for pair with the oracle's hash join (the oracle calls
+  run in a thread pool; they release the GIL).
+* 128 independent tiny joins (655 MB) in one batch.
+* The continuous-batching server over the resident 10M-key build side with
+  requests of up to 1M keys, and the partitioned host-memory join.
+
+Join outputs are exact multisets of integer pairs; signatures of sampled
+keys are compared bit for bit.  On every output, properties that hold at any
+size are checked as well: no pair twice, ids inside their join.
 """
 import numpy as np
 import pytest
@@ -41,16 +47,16 @@ def unique_pairs(p):
     return len(np.unique(key)) == len(key)
 
 
-def keys_equal(R, S, pairs, rng, count=20000, r_base=0, s_base=0):
-    """Byte-compare the keys of up to `count` sampled emitted pairs."""
-    if len(pairs) == 0:
-        return True
-    pick = rng.choice(len(pairs), size=min(count, len(pairs)), replace=False)
-    return all(R.key(r_base + int(pairs[i, 0])) == S.key(s_base + int(pairs[i, 1])) for i in pick)
-
-
 def gpu_signatures(A, keys):
     return A.asj_signature(keys).cpu().numpy().view(np.uint32).astype(np.uint64)
+
+
+# Probe configurations the autotuner may choose for a single join with a
+# device-memory table (load factor, keys per window, grid rounds, schedule),
+# beside the library defaults and the autotuner's own choice.
+BENCH_CONFIGS = ([dict(load_factor=0.25, keys_per_window=k, grid_rounds=g) for k in (16, 32, 64) for g in (1, 2, 4)]
+                 + [dict(load_factor=lf, keys_per_window=32, grid_rounds=1) for lf in (0.35, 0.5, 0.7)]
+                 + [dict(load_factor=0.25, keys_per_window=32, grid_rounds=1, split=True)])
 
 
 @pytest.mark.parametrize("name", ["large", "dna"])
@@ -60,17 +66,33 @@ def test_full_size_join_equals_oracle(A, oracle, wl, name):
     note(f"{name}: R={w.R.n} S={w.S.n} bytes={w.R.nbytes + w.S.nbytes}")
     Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
     expected = int(w.meta["expected_matches"])
-    out = torch.empty((expected + 1024, 2), dtype=torch.int32, device="cuda")  # the benchmark's capacity
+    cap = expected + 1024  # the benchmark's capacity
+    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
     counts = torch.zeros(2, dtype=torch.int64, device="cuda")
-    A.asj_join(Rk, Sk, out, counts)
-    total = int(counts[0])
-    assert 0 <= total <= expected + 1024
-    got = out[:total].cpu().numpy()
-    note(f"{name}: GPU |T|={total}; oracle join")
-    want = oracle.join_hash(w.R, w.S, cap=expected + 1024)
-    assert total == len(want) == expected
-    assert np.array_equal(oracle.sort_pairs(got), want)
-    assert unique_pairs(got)
+    note(f"{name}: oracle signature join")
+    want, want_cand = oracle.join_signature(w.R, w.S, cap=cap)
+    assert len(want) == expected
+
+    def check(label, **kw):
+        counts.zero_()
+        A.asj_join(Rk, Sk, out, counts, **kw)
+        total, ncand = (int(x) for x in counts.tolist())
+        assert total == expected, (label, total)
+        got = out[:total].cpu().numpy()
+        assert np.array_equal(oracle.sort_pairs(got), want), label
+        assert ncand == want_cand, (label, ncand, want_cand)
+        assert unique_pairs(got), label
+
+    check("defaults")
+    tune = A.autotune(Rk, Sk, out, counts)  # the benchmark's setup; later calls leave the options to the library
+    note(f"{name}: autotuner chose {tune}")
+    check("autotuned")
+    A.autotune_clear()
+    for cfg in BENCH_CONFIGS:
+        cfg = dict(cfg)
+        flags = A.ASJ_PROBE_SPLIT if cfg.pop("split", False) else A.ASJ_PROBE_FUSED
+        check(str(cfg), flags=flags | A.ASJ_GLOBAL_TABLES, **cfg)
+    note(f"{name}: {len(BENCH_CONFIGS) + 2} configurations equal the oracle (|T|={expected}, candidates={want_cand})")
     rng = np.random.default_rng([17, len(name)])
     for rel, keys in ((w.R, Rk), (w.S, Sk)):
         sig = gpu_signatures(A, keys)
@@ -78,29 +100,68 @@ def test_full_size_join_equals_oracle(A, oracle, wl, name):
         assert np.array_equal(sig[idx], oracle.signatures(rel.subset(idx)))
 
 
-def test_full_size_batch_sampled_joins_equal_oracle(A, oracle, wl):
+def oracle_batch(oracle, b, workers=None):
+    """The oracle's signature join of every join of a batch workload, as
+    (sorted pairs, candidate count) per join.  Join k is passed as views of
+    the batch arena (its offsets slice and row-local ids); the C calls
+    release the GIL, so the joins run in a thread pool."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(k):
+        r0, r1, s0, s1 = (int(x) for x in (b.r_seg[k], b.r_seg[k + 1], b.s_seg[k], b.s_seg[k + 1]))
+        R = (b.R.data, b.R.offsets[r0:r1 + 1], b.R.ids[r0:r1])
+        S = (b.S.data, b.S.offsets[s0:s1 + 1], b.S.ids[s0:s1])
+        return oracle.join_signature(R, S, cap=(s1 - s0) + 1024)
+
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    # largest joins first, so the pool does not end on one long join
+    order = sorted(range(b.njoins), key=lambda k: -(b.s_seg[k + 1] - b.s_seg[k]))
+    with ThreadPoolExecutor(workers) as ex:
+        res = dict(zip(order, ex.map(one, order)))
+    return [res[k] for k in range(b.njoins)]
+
+
+def check_batch_output(oracle, b, want, outh, oseg, counts, cands, label):
+    rsz, ssz = np.diff(b.r_seg), np.diff(b.s_seg)
+    for k in range(b.njoins):
+        wp, wc = want[k]
+        assert counts[k] == len(wp), (label, k, counts[k], len(wp))
+        assert counts[k] <= oseg[k + 1] - oseg[k], (label, k)
+        p = outh[oseg[k]:oseg[k] + counts[k]]
+        assert ((p[:, 0] >= 0) & (p[:, 0] < rsz[k]) & (p[:, 1] >= 0) & (p[:, 1] < ssz[k])).all(), (label, k)
+        assert np.array_equal(oracle.sort_pairs(p), wp), (label, k)
+        assert cands[k] == wc, (label, k, cands[k], wc)
+
+
+def test_full_size_batch_all_joins_equal_oracle(A, oracle, wl):
+    """All 256 joins of the full-size batched workload, in the library's
+    default configuration and in the autotuner's choice (what the benchmark
+    times), each compared pair for pair with the oracle, candidate counts
+    included."""
+    import torch
     b = wl.batch()
     note(f"batch: joins={b.njoins} R={b.R.n} S={b.S.n} bytes={b.R.nbytes + b.S.nbytes}")
     R, S = A.DeviceKeys.from_host(b.R), A.DeviceKeys.from_host(b.S)
-    out, oseg, counts, _, _ = A.join_batch(R, S, b.r_seg, b.s_seg)
+    out, oseg, counts, cands, _ = A.join_batch(R, S, b.r_seg, b.s_seg)
     outh = out.cpu().numpy()
-    rsz, ssz = np.diff(b.r_seg), np.diff(b.s_seg)
+    note("batch: oracle joins")
+    want = oracle_batch(oracle, b)
+    check_batch_output(oracle, b, want, outh, oseg, counts, cands, "defaults")
+    note(f"batch: all {b.njoins} joins equal the oracle; {int(counts.sum())} pairs")
+    dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
+    r_seg, s_seg, out_seg = dev(b.r_seg), dev(b.s_seg), dev(oseg)
+    J = b.njoins
+    tune = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"))
+    note(f"batch: autotuner chose {tune}")
+    cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
+    cnd = torch.zeros(J, dtype=torch.int64, device="cuda")
+    ws = torch.empty(A.asj_batch_workspace_bytes(J, b.R.n, b.S.n), dtype=torch.uint8, device="cuda")
+    out.fill_(-7)
+    A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, cnd, None, workspace=ws)
+    check_batch_output(oracle, b, want, out.cpu().numpy(), oseg, cnt.cpu().numpy(), cnd.cpu().numpy(), "autotuned")
+    A.autotune_clear()
     rng = np.random.default_rng(23)
-    for k in range(b.njoins):  # properties of every join's output
-        p = outh[oseg[k]:oseg[k] + counts[k]]
-        assert counts[k] <= oseg[k + 1] - oseg[k], k
-        assert ((p[:, 0] >= 0) & (p[:, 0] < rsz[k]) & (p[:, 1] >= 0) & (p[:, 1] < ssz[k])).all(), k
-        assert unique_pairs(p), k
-        assert keys_equal(b.R, b.S, p, rng, count=200, r_base=int(b.r_seg[k]), s_base=int(b.s_seg[k])), k
-    sample = set(rng.choice(b.njoins, size=24, replace=False).tolist())
-    sample |= {int(np.argmax(ssz)), int(np.argmin(ssz))}
-    for k in sorted(sample):
-        j = b.join(k)
-        want = oracle.join_hash(j.R, j.S, cap=j.S.n + 1024)
-        got = outh[oseg[k]:oseg[k] + counts[k]]
-        assert counts[k] == len(want), k
-        assert np.array_equal(oracle.sort_pairs(got), want), k
-    note(f"batch: {len(sample)} joins equal the oracle; {int(counts.sum())} pairs in all")
     idx = np.sort(rng.choice(b.S.n, size=20000, replace=False))
     assert np.array_equal(gpu_signatures(A, S)[idx], oracle.signatures(b.S.subset(idx)))
 
@@ -166,8 +227,8 @@ def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
     """128 independent tiny joins (R = S = 10k keys of 256 B each, 655 MB) in
     one batch, the benchmark's throughput configuration (every join's table
     built in LDS; options left to the library): every join has exactly the
-    generator's 2000 matches, every output has the properties above, and a
-    seeded sample of whole joins equals the oracle pair for pair."""
+    generator's 2000 matches and equals the oracle pair for pair, candidate
+    counts included."""
     parts = [wl.tiny(seed=1 + i) for i in range(128)]
     def cat(rels):
         lens = np.concatenate([r.lengths() for r in rels])
@@ -178,19 +239,10 @@ def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
     Rf, Sf = cat([p.R for p in parts]), cat([p.S for p in parts])
     r_seg = np.concatenate([[0], np.cumsum([p.R.n for p in parts])]).astype(np.int64)
     s_seg = np.concatenate([[0], np.cumsum([p.S.n for p in parts])]).astype(np.int64)
+    b = wl.BatchWorkload("tiny x128", Rf, Sf, r_seg, s_seg)
     note(f"tiny instances: joins=128 R={Rf.n} S={Sf.n} bytes={Rf.nbytes + Sf.nbytes}")
     R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
     out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg)
     assert (counts == 2000).all()
-    outh = out.cpu().numpy()
-    rng = np.random.default_rng(29)
-    for k, w in enumerate(parts):
-        p = outh[oseg[k]:oseg[k] + counts[k]]
-        assert ((p[:, 0] >= 0) & (p[:, 0] < w.R.n) & (p[:, 1] >= 0) & (p[:, 1] < w.S.n)).all(), k
-        assert unique_pairs(p), k
-        assert keys_equal(w.R, w.S, p, rng, count=100), k
-    for k in sorted(rng.choice(128, size=12, replace=False).tolist()):
-        want, want_cand = oracle.join_signature(parts[k].R, parts[k].S)
-        assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want), k
-        assert cands[k] == want_cand, k
-    note("tiny instances: 128 joins with 2000 pairs each; 12 sampled joins equal the oracle")
+    check_batch_output(oracle, b, oracle_batch(oracle, b), out.cpu().numpy(), oseg, counts, cands, "tiny x128")
+    note("tiny instances: all 128 joins (2000 pairs each) equal the oracle")

@@ -586,3 +586,106 @@ def test_single_join_at_the_lds_table_limit(A, oracle, wl, m):
         got, total, _ = gpu_join(A, w.R, w.S, flags=KINDS[kind])
         want = oracle.join_variant(w.R, w.S, kind)
         assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want), kind
+
+
+# ---------------------------------------------------------------------------
+# Arenas without padding: the header promises that `data` needs none (only
+# 4-byte words holding key bytes are read), and a key's bytes must be masked
+# against whatever follows it.  The keys go into device buffers whose bytes
+# before the first key and after offsets[n] are non-zero junk, or into a
+# buffer of exactly offsets[n] bytes.
+# ---------------------------------------------------------------------------
+
+def junk_keys(A, rel, shift, junk, exact=False):
+    import torch
+    off = rel.offsets - rel.offsets[0]
+    nbytes = int(off[-1])
+    body = torch.from_numpy(np.ascontiguousarray(rel.data[rel.offsets[0]:rel.offsets[0] + nbytes]))
+    if exact:
+        buf = torch.empty(shift + nbytes, dtype=torch.uint8, device="cuda")
+    else:
+        buf = torch.empty(shift + nbytes + 67, dtype=torch.uint8, device="cuda")
+    g = torch.Generator().manual_seed(int(junk))
+    buf.copy_(torch.randint(1, 256, (buf.numel(),), dtype=torch.uint8, generator=g))  # never zero
+    if nbytes:
+        buf[shift:shift + nbytes].copy_(body)
+    offs = torch.from_numpy(off + shift).cuda()
+    ids = torch.from_numpy(rel.ids).cuda() if rel.ids is not None else None
+    return A.DeviceKeys(buf, offs, ids)
+
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("shift", [0, 1, 3, 6])
+@pytest.mark.parametrize("params", [(16, 2), (16, 1), (8, 4), (8, 2), (16, 4)])
+def test_signature_no_padding_junk_around_keys(A, oracle, wl, shift, params, exact):
+    rng = np.random.default_rng(300 + shift)
+    keys = adversarial_keys(rng)[:150] + [b"x" * L for L in (1, 2, 3, 5, 63, 65, 127)]
+    rel = wl.from_keys(keys)
+    f, nsym = params
+    out = A.asj_signature(junk_keys(A, rel, shift, 1000 + shift, exact), f, nsym).cpu().numpy()
+    got = out.view(np.uint64) if f * nsym == 64 else out.view(np.uint32).astype(np.uint64)
+    assert np.array_equal(got, oracle.signatures(rel, f, nsym))
+
+
+def junk_join_relations(wl, seed):
+    rng = np.random.default_rng([seed, 42])
+    def mk(count, max_len):
+        lens = rng.integers(0, max_len + 1, size=count)
+        short = rng.uniform(size=count) < 0.4
+        lens[short] = rng.integers(0, 70, size=int(short.sum()))
+        return [rng.integers(0, 3, size=int(L), dtype=np.uint8).tobytes() for L in lens]
+    rk = mk(700 + 13 * seed, 300)
+    sk = mk(1500 + 29 * seed, 300)
+    for i in range(len(sk)):
+        if rng.uniform() < 0.35:
+            sk[i] = rk[int(rng.integers(0, len(rk)))]
+    # the last key of each relation is short, so its tail is read at the arena's end
+    rk[-1] = rk[-1][:1 + seed % 60]
+    sk[-1] = sk[-1][:2 + seed % 50]
+    return wl.from_keys(rk), wl.from_keys(sk)
+
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("mode", ["split", "fused", "fused_global", "plain", "sig64"])
+@pytest.mark.parametrize("seed", range(3))
+def test_join_no_padding_junk_around_keys(A, oracle, wl, seed, mode, exact):
+    import torch
+    R, S = junk_join_relations(wl, seed)
+    kw = {}
+    if mode == "plain":
+        kw["flags"] = A.ASJ_PLAIN
+    elif mode == "sig64":
+        kw.update(nsym=4, flags=A.ASJ_PROBE_FUSED | A.ASJ_GLOBAL_TABLES)
+    else:
+        kw["flags"] = sched_flag(A, mode)
+    Rk = junk_keys(A, R, 1 + seed, 2000 + seed, exact)
+    Sk = junk_keys(A, S, 3 + seed, 3000 + seed, exact)
+    pairs, total, ncand = A.join(Rk, Sk, **kw)
+    want = oracle.join_nested(R, S)
+    assert total == len(want)
+    assert np.array_equal(oracle.sort_pairs(pairs.cpu().numpy()), want)
+    if mode != "plain":
+        _, want_cand = oracle.join_signature(R, S, 16, 4 if mode == "sig64" else 2)
+        assert ncand == want_cand
+
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("flags", ["default", "global", "plain"])
+def test_batch_no_padding_junk_around_keys(A, oracle, wl, flags, exact):
+    parts = [junk_join_relations(wl, s) for s in range(5)]
+    def cat(rels):
+        keys = [r.key(k) for r in rels for k in range(r.n)]
+        return wl.from_keys(keys, np.concatenate([r.ids for r in rels]))
+    Rf, Sf = cat([p[0] for p in parts]), cat([p[1] for p in parts])
+    r_seg = np.concatenate([[0], np.cumsum([p[0].n for p in parts])]).astype(np.int64)
+    s_seg = np.concatenate([[0], np.cumsum([p[1].n for p in parts])]).astype(np.int64)
+    fl = {"default": 0, "global": A.ASJ_GLOBAL_TABLES, "plain": A.ASJ_PLAIN}[flags]
+    out, oseg, counts, cands, _ = A.join_batch(junk_keys(A, Rf, 2, 51, exact), junk_keys(A, Sf, 5, 52, exact),
+                                               r_seg, s_seg, flags=fl)
+    outh = out.cpu().numpy()
+    for k, (R, S) in enumerate(parts):
+        want, want_cand = oracle.join_signature(R, S)
+        assert counts[k] == len(want), k
+        assert np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + counts[k]]), want), k
+        if flags != "plain":
+            assert cands[k] == want_cand, k

@@ -102,3 +102,38 @@ def test_decreasing_offsets_are_refused_at_submission(A):
         s.submit(d, o, out)
     assert e.value.code == A.ASJ_EINVAL
     s.close()
+
+
+def test_second_waiter_on_a_ticket_is_refused(A):
+    """One waiter per ticket: while one thread waits, a second wait on the same
+    ticket returns ASJ_EINVAL at once (it must not share the request the first
+    waiter frees); after the first wait the ticket is released."""
+    import threading
+    s = A.Server(None, dry_run=True, dry_ns_per_key=20000.0)  # ~40 ms for 2000 keys
+    d, o, out = request(2000)
+    t = s.submit(d, o, out)
+    first = {}
+    th = threading.Thread(target=lambda: first.update(s.wait(t)))
+    th.start()
+    import time
+    time.sleep(0.01)
+    assert s.wait(t)["status"] == A.ASJ_EINVAL
+    th.join()
+    assert first["status"] == 0
+    assert s.wait(t)["status"] == A.ASJ_EINVAL  # released
+    s.close()
+
+
+def test_submit_checks_buffers(A):
+    s = A.Server(None, dry_run=True, dry_ns_per_key=10.0)
+    d, o, out = request(100)
+    with pytest.raises(ValueError):
+        s.submit(d, o, out, out_cap=out.shape[0] + 1)  # more rows than out holds
+    with pytest.raises(ValueError):
+        s.submit(d, o.astype(np.int32), out)
+    with pytest.raises(ValueError):
+        s.submit(d.astype(np.int16), o, out)
+    with pytest.raises(ValueError):
+        s.submit(d, o, out.astype(np.int64))
+    s.wait(s.submit(d, o, out, out_cap=10))
+    s.close()
