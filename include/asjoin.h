@@ -216,6 +216,33 @@ int asj_probe(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_
 int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
              int64_t *out_count, int64_t *cand_count, hipStream_t stream);
 
+/* ---- a join that allocates nothing ---- */
+
+#define ASJ_NOALLOC_MAX_BUILD_ROWS 10240
+#define ASJ_NOALLOC_SCRATCH_BYTES 65536
+
+/* asj_join for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or allocating library routine: the build side's
+ * signatures, status words and right-outer marks live in a fixed device
+ * array of ASJ_NOALLOC_SCRATCH_BYTES bytes that the library holds on every
+ * device it runs on until the process ends (the GF constant tables, too,
+ * live in the library's own device array).  Limits: at most
+ * ASJ_NOALLOC_MAX_BUILD_ROWS build rows (r->n larger: ASJ_EINVAL), where the
+ * table is built in LDS by every probing block exactly as asj_join builds
+ * it for such build sides; the fused probe schedule only.
+ * Arguments, output and errors are those of asj_join, except that
+ * ASJ_SORTED, ASJ_GLOBAL_TABLES and ASJ_PROBE_SPLIT are refused
+ * (ASJ_EINVAL) and the fingerprint control and 64-bit signatures are
+ * ASJ_EUNSUPPORTED.  Every call on a device shares that device's one scratch
+ * array, which each call clears before use: calls that overlap on one device
+ * (different streams, or host threads) race and may report wrong results;
+ * order them on one stream.  The first call of the process on a device
+ * initialises the library there (constant tables, which synchronizes the
+ * device): make it outside graph capture. */
+int asj_join_noalloc(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+                     int64_t *out_count, int64_t *cand_count, hipStream_t stream);
+
 /* ---- many independent joins in one launch sequence ---- */
 
 /* A batch of J independent equi-joins T_j = Join(R_j, S_j) (each one is the

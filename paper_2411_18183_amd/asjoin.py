@@ -96,6 +96,7 @@ def lib():
         L.asj_probe.argtypes = [P, ctypes.POINTER(asj_keys), P, I64, P, P, P]
         L.asj_join.argtypes = [ctypes.POINTER(asj_keys), ctypes.POINTER(asj_keys), ctypes.POINTER(asj_opts), P, I64,
                                P, P, P]
+        L.asj_join_noalloc.argtypes = L.asj_join.argtypes
         L.asj_table_status.argtypes = [P]
         L.asj_table_capacity.argtypes = [P]
         L.asj_table_capacity.restype = I64
@@ -119,7 +120,8 @@ def lib():
         L.asj_join_host_release.argtypes = []
         L.asj_clock_khz.argtypes = []
         L.asj_clock_khz.restype = I64
-        for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_table_status", "asj_table_free",
+        for name in ("asj_signature", "asj_build", "asj_probe", "asj_join", "asj_join_noalloc", "asj_table_status",
+                     "asj_table_free",
                      "asj_timing_enable", "asj_timing_read", "asj_util_copy", "asj_join_batch", "asj_autotune",
                      "asj_autotune_batch", "asj_join_host", "asj_join_host_release"):
             getattr(L, name).restype = ctypes.c_int
@@ -266,6 +268,26 @@ def asj_join(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tens
     _check(lib().asj_join(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
                           ctypes.c_void_p(out.data_ptr() if cap else None), cap, ctypes.c_void_p(counts.data_ptr()),
                           ctypes.c_void_p(counts.data_ptr() + 8), _stream(stream)), "asj_join")
+
+
+ASJ_NOALLOC_MAX_BUILD_ROWS = 10240
+ASJ_NOALLOC_SCRATCH_BYTES = 65536
+
+
+def asj_join_noalloc(R: DeviceKeys, S: DeviceKeys, out: torch.Tensor, counts: torch.Tensor, f: int = 16,
+                     nsym: int = 2, load_factor: float = 0.0, flags: int = 0, keys_per_window: int = 0,
+                     grid_rounds: int = 0, stream=None):
+    """asj_join for at most ASJ_NOALLOC_MAX_BUILD_ROWS build rows without any device allocation (the
+    library's fixed scratch array; calls overlapping on one device race).  out: int32 [cap, 2];
+    counts: int64 [2] -> (|T|, candidates)."""
+    kr, ks = R.c(), S.c()
+    o = _opts(f, nsym, load_factor, flags, keys_per_window, grid_rounds)
+    cap = _need_pairs(out, "asj_join_noalloc out")
+    _need_dev(counts, torch.int64, 2, "asj_join_noalloc counts")
+    _check(lib().asj_join_noalloc(ctypes.byref(kr), ctypes.byref(ks), ctypes.byref(o),
+                                  ctypes.c_void_p(out.data_ptr() if cap else None), cap,
+                                  ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(counts.data_ptr() + 8),
+                                  _stream(stream)), "asj_join_noalloc")
 
 
 def join(R: DeviceKeys, S: DeviceKeys, cap: Optional[int] = None, **kw):

@@ -16,9 +16,27 @@ constexpr int kSignGridCap = 256 * 16;  // blocks; the sign kernel loops over wi
 constexpr int kProbeGridCap = 256 * 16;
 
 struct DeviceState {
-    uint16_t *tab = nullptr; // GF constant tables (device)
+    uint16_t *tab = nullptr;    // GF constant tables: this device's copy of gf_tab
+    uint8_t *scratch = nullptr; // asj_join_noalloc's scratch: this device's copy of `scratch`
     bool ready = false;
 };
+
+// Both arrays live in the code object, so every device that loads the
+// library holds a copy of each until the process ends and the library never
+// allocates them.  Host code reaches them only through the per-device
+// addresses that hipGetSymbolAddress returns at initialisation (the names
+// themselves are host-side stand-ins, not device addresses).
+static __device__ __align__(256) uint16_t gf_tab[ASJ_TAB_TOTAL_WORDS];
+// Scratch of asj_join_noalloc: status word, build signatures, probe status
+// word and right-outer marks of one join with at most
+// ASJ_NOALLOC_MAX_BUILD_ROWS build rows (layout: noalloc_layout).
+static __device__ __align__(256) uint8_t scratch[ASJ_NOALLOC_SCRATCH_BYTES];
+static_assert(ASJ_NOALLOC_MAX_BUILD_ROWS == ASJ_LOCAL_ROWS, "asj_join_noalloc takes the LDS-table path only");
+// status word, signatures, probe status word, right-outer marks (local_layout) at the row limit
+static_assert(256 + ((4 * ASJ_NOALLOC_MAX_BUILD_ROWS + 255) / 256 * 256) + 256 +
+                      ((ASJ_NOALLOC_MAX_BUILD_ROWS + 255) / 256 * 256) <=
+                  ASJ_NOALLOC_SCRATCH_BYTES,
+              "scratch too small for the largest build side");
 
 std::mutex g_mu;
 DeviceState g_dev[kMaxDevices];
@@ -82,12 +100,12 @@ int ensure_init(int *dev_out)
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceState &d = g_dev[dev];
     if (d.ready) return ASJ_OK;
+    // this device's copies of the two arrays (the device is current here)
     uint16_t *tab = nullptr;
-    if (hipMalloc((void **)&tab, sizeof(uint16_t) * ASJ_TAB_TOTAL_WORDS) != hipSuccess) return ASJ_ENOMEM;
-    if (asj_launch_tables(tab, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(tab);
-        return ASJ_EHIP;
-    }
+    uint8_t *scr = nullptr;
+    if (hipGetSymbolAddress((void **)&tab, HIP_SYMBOL(gf_tab)) != hipSuccess || !tab) return ASJ_EHIP;
+    if (hipGetSymbolAddress((void **)&scr, HIP_SYMBOL(scratch)) != hipSuccess || !scr) return ASJ_EHIP;
+    if (asj_launch_tables(tab, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return ASJ_EHIP;
     // keep freed stream-ordered blocks cached in the default pool
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -95,6 +113,7 @@ int ensure_init(int *dev_out)
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
     d.tab = tab;
+    d.scratch = scr;
     d.ready = true;
     return ASJ_OK;
 }
@@ -278,13 +297,13 @@ int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out
 {
     int rc = probe_unsorted(t, s, out, out_cap, out_count, cand_count, st);
     if (rc != ASJ_OK || !t->sorted || out_cap == 0) return rc;
-    void *scratch = nullptr;
-    hipError_t e = hipMallocAsync(&scratch, asj_sort_scratch_bytes(out_cap), st);
+    void *sort_tmp = nullptr;
+    hipError_t e = hipMallocAsync(&sort_tmp, asj_sort_scratch_bytes(out_cap), st);
     if (e != hipSuccess) return hip_fail(e);
     tim_begin("sort", st);
-    e = asj_launch_sort_pairs(out, out_count, out_cap, scratch, st);
+    e = asj_launch_sort_pairs(out, out_count, out_cap, sort_tmp, st);
     tim_end(st);
-    (void)hipFreeAsync(scratch, st);
+    (void)hipFreeAsync(sort_tmp, st);
     return e == hipSuccess ? ASJ_OK : hip_fail(e);
 }
 
@@ -491,8 +510,25 @@ constexpr int kNotLocal = 1; // join_local_single: not this path
 // device-memory table, no insert).  Returns kNotLocal when the options ask
 // for a path it does not take (device-memory tables, the split schedule,
 // 64-bit signatures, the fingerprint control).
+// Scratch layout of one such join: status word | build signatures | probe
+// status word | right-outer marks, each part 256-byte aligned.
+struct LocalLayout {
+    size_t sig, pst, rm, bytes;
+};
+LocalLayout local_layout(int64_t n_build, int64_t rwords)
+{
+    LocalLayout L;
+    L.sig = 256;
+    L.pst = align256(L.sig + 4 * (size_t)(n_build > 0 ? n_build : 1));
+    L.rm = align256(L.pst + 4);
+    L.bytes = align256(L.rm + 4 * (size_t)(rwords > 0 ? rwords : 1));
+    return L;
+}
+
+// fixed: the caller's scratch (asj_join_noalloc: nothing is allocated,
+// ASJ_SORTED is refused); NULL: one stream-ordered allocation.
 int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
-                      int64_t *out_count, int64_t *cand_count, hipStream_t st)
+                      int64_t *out_count, int64_t *cand_count, hipStream_t st, uint8_t *fixed = nullptr)
 {
     if (!keys_ok(r) || r->n > ASJ_LOCAL_ROWS) return kNotLocal;
     asj_opts o = {};
@@ -514,15 +550,19 @@ int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts
     if (rc != ASJ_OK) return rc;
     const bool marks = asj_kind_marks_build(kind);
     const int64_t rwords = marks ? (r->n + 3) / 4 : 0;
-    const size_t o_sig = 256, o_pst = align256(o_sig + 4 * (size_t)(r->n > 0 ? r->n : 1));
-    const size_t o_rm = align256(o_pst + 4), bytes = align256(o_rm + 4 * (size_t)(rwords > 0 ? rwords : 1));
-    uint8_t *blk = nullptr;
-    hipError_t e = hipMallocAsync((void **)&blk, bytes, st);
-    if (e != hipSuccess) return hip_fail(e);
+    const LocalLayout L = local_layout(r->n, rwords);
+    uint8_t *blk = fixed;
+    hipError_t e = hipSuccess;
+    if (fixed) {
+        if (L.bytes > ASJ_NOALLOC_SCRATCH_BYTES || (o.flags & ASJ_SORTED)) return ASJ_EINVAL;
+    } else {
+        e = hipMallocAsync((void **)&blk, L.bytes, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
     int32_t *status = (int32_t *)blk;
-    uint32_t *sig_r = (uint32_t *)(blk + o_sig);
-    int32_t *pstatus = (int32_t *)(blk + o_pst);
-    uint8_t *rmatch = marks ? blk + o_rm : nullptr;
+    uint32_t *sig_r = (uint32_t *)(blk + L.sig);
+    int32_t *pstatus = (int32_t *)(blk + L.pst);
+    uint8_t *rmatch = marks ? blk + L.rm : nullptr;
     const int validate = (o.flags & ASJ_VALIDATE) != 0;
     int out_rc = ASJ_OK;
     do {
@@ -575,17 +615,17 @@ int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         }
         if ((o.flags & ASJ_SORTED) && out_cap > 0) {
-            void *scratch = nullptr;
-            e = hipMallocAsync(&scratch, asj_sort_scratch_bytes(out_cap), st);
+            void *sort_tmp = nullptr;
+            e = hipMallocAsync(&sort_tmp, asj_sort_scratch_bytes(out_cap), st);
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
             tim_begin("sort", st);
-            e = asj_launch_sort_pairs(out, out_count, out_cap, scratch, st);
+            e = asj_launch_sort_pairs(out, out_count, out_cap, sort_tmp, st);
             tim_end(st);
-            (void)hipFreeAsync(scratch, st);
+            (void)hipFreeAsync(sort_tmp, st);
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         }
     } while (0);
-    (void)hipFreeAsync(blk, st);
+    if (!fixed) (void)hipFreeAsync(blk, st);
     return out_rc;
 }
 
@@ -636,6 +676,36 @@ int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pai
     rc = probe_impl(t, s, out, out_cap, out_count, cand_count, st);
     int rc2 = table_free_impl(t);
     return rc != ASJ_OK ? rc : rc2;
+}
+
+int asj_join_noalloc(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,
+                     int64_t *out_count, int64_t *cand_count, hipStream_t st)
+{
+    TimingScope ts;
+    if (!keys_ok(r) || !keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
+    if (r->n > ASJ_NOALLOC_MAX_BUILD_ROWS) return ASJ_EINVAL; // beyond the scratch array
+    asj_opts o = {};
+    if (opts) o = *opts;
+    // options that would allocate: sorting, a device-memory table, the split schedule
+    if (o.flags & (ASJ_SORTED | ASJ_GLOBAL_TABLES | ASJ_PROBE_SPLIT)) return ASJ_EINVAL;
+    o.flags |= ASJ_PROBE_FUSED; // also when the autotuner recorded the split schedule for this size
+    const int plain = (o.flags & ASJ_PLAIN) != 0, verify = (o.flags & ASJ_NO_VERIFY) == 0;
+    if ((plain && !verify) || join_kind(o.flags) < 0) return ASJ_EINVAL;
+    if (o.flags & ASJ_FINGERPRINT) return ASJ_EUNSUPPORTED;
+    if (!plain) {
+        asj_sig_params sig;
+        const int src = resolve_sig(o.sig, &sig);
+        if (src != ASJ_OK) return src;
+        if (sig64(sig)) return ASJ_EUNSUPPORTED;
+    }
+    float lf;
+    int kpw, split, rounds;
+    if (resolve_auto(0, r->n, o, &lf, &kpw, &split, &rounds) != ASJ_OK) return ASJ_EINVAL;
+    int dev = 0;
+    const int rc = ensure_init(&dev);
+    if (rc != ASJ_OK) return rc;
+    const int lrc = join_local_single(r, s, &o, out, out_cap, out_count, cand_count, st, g_dev[dev].scratch);
+    return lrc == kNotLocal ? ASJ_EINVAL : lrc; // (every option set left reaches the LDS-table path)
 }
 
 int asj_table_status(const asj_table *t)

@@ -117,3 +117,19 @@ def test_header_constants_match_the_binding():
     for name, val in defs.items():
         assert hasattr(A, name), name
         assert getattr(A, name) == int(val, 0), name
+
+
+def test_noalloc_refuses_oversized_build_side_before_device_work(lib):
+    """asj_join_noalloc rejects a build side beyond its fixed scratch array
+    (and NULL arguments) on the host, before any device call."""
+    class Keys(ctypes.Structure):
+        _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                    ("n", ctypes.c_int64)]
+    lib.asj_join_noalloc.restype = ctypes.c_int
+    dummy = ctypes.c_int64(0)
+    r = Keys(None, ctypes.addressof(dummy), None, 10241)  # pointers are never dereferenced
+    s = Keys(None, ctypes.addressof(dummy), None, 1)
+    cnt = ctypes.c_int64(0)
+    assert lib.asj_join_noalloc(ctypes.byref(r), ctypes.byref(s), None, None, ctypes.c_int64(0),
+                                ctypes.byref(cnt), None, None) == -1
+    assert lib.asj_join_noalloc(None, None, None, None, ctypes.c_int64(0), None, None, None) == -1
