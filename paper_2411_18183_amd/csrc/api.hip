@@ -179,16 +179,31 @@ int resolve_auto(int batch, int64_t n_build, const asj_opts &o, float *lf, int *
 }
 
 // out_hi / stride: see asj_launch_sign (four GF(2^16) components only).
+// kpw: the join's keys per window, also used for signing (see sign.hip).
 hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uint32_t *out, const uint16_t *tab,
                            hipStream_t st, const int32_t *status = nullptr, uint32_t *out_hi = nullptr,
-                           int stride = 1, const asj_batch_prep *prep = nullptr)
+                           int stride = 1, const asj_batch_prep *prep = nullptr, int kpw = ASJ_WAVE)
 {
-    if (plain) return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status, nullptr, 1, prep);
+    if (plain)
+        return asj_launch_sign(ASJ_MODE_PLAIN, 1, k, out, tab, kSignGridCap, st, status, nullptr, 1, prep, kpw);
     return asj_launch_sign(sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8, sig.nsym, k, out, tab, kSignGridCap, st,
-                           status, out_hi, stride, prep);
+                           status, out_hi, stride, prep, kpw);
 }
 
 bool sig64(asj_sig_params s) { return s.f == 16 && s.nsym == 4; }
+
+// Keys per window for signing n keys on their own (the build side, or
+// asj_signature): 64, halved while that leaves fewer than 2048 windows,
+// down to 16, unless n is small enough for an LDS table (a latency-bound
+// join, whose few blocks load the GF tables only once each).  Few keys are
+// usually long ones: 32k keys of 4 KB in windows of 64 kept one eighth of
+// the compute units busy.
+int sign_kpw_for(int64_t n)
+{
+    int kpw = ASJ_WAVE;
+    while (kpw > 16 && n > ASJ_LOCAL_ROWS && n / kpw < 2048) kpw >>= 1;
+    return kpw;
+}
 
 template <typename T>
 hipError_t alloc_async(T **p, size_t count, hipStream_t st)
@@ -272,7 +287,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin(plain ? "hash_build" : fp ? "fp_build" : "sign_build", st);
-        le = launch_sign_for(r, sig, plain || fp, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi);
+        le = launch_sign_for(r, sig, plain || fp, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi, 1, nullptr,
+                             sign_kpw_for(r->n));
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
@@ -374,7 +390,8 @@ int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t
         e = alloc_async(&ssig, (size_t)s->n, st);
         if (e == hipSuccess) {
             tim_begin(t->plain ? "hash_S" : t->fp ? "fp_S" : "sign_S", st);
-            e = launch_sign_for(s, t->sig, t->plain || t->fp, ssig, g_dev[dev].tab, st, pstatus);
+            e = launch_sign_for(s, t->sig, t->plain || t->fp, ssig, g_dev[dev].tab, st, pstatus, nullptr, 1, nullptr,
+                                t->keys_per_window);
             tim_end(st);
         }
         if (e == hipSuccess) {
@@ -576,7 +593,7 @@ int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, status);
+        e = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, nullptr, sign_kpw_for(r->n));
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         asj_probe_args a = {};
@@ -643,10 +660,12 @@ int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hip
     int dev = 0;
     rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
+    const int kpw = sign_kpw_for(keys->n);
     if (sig64(sig)) // little-endian 64-bit signatures: the low word, then the high word
-        TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st, nullptr, sig_out + 1, 2));
+        TIMED("signature",
+              launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st, nullptr, sig_out + 1, 2, nullptr, kpw));
     else
-        TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st));
+        TIMED("signature", launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st, nullptr, nullptr, 1, nullptr, kpw));
     return ASJ_OK;
 }
 
@@ -849,7 +868,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
                                win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap,
                                (uint32_t *)rmatch, rmatch ? (b->r.n + 3) / 4 : 0};
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep);
+        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep,
+                            sign_kpw_for(b->r.n));
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin("insert", st);
@@ -888,7 +908,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         const int mode = plain ? ASJ_MODE_PLAIN : (sig.f == 16 ? ASJ_MODE_SIG16 : ASJ_MODE_SIG8);
         if (split && b->s.n > 0) {
             tim_begin(plain ? "hash_S" : "sign_S", st);
-            e = launch_sign_for(&b->s, sig, plain, sig_s, g_dev[dev].tab, st, status);
+            e = launch_sign_for(&b->s, sig, plain, sig_s, g_dev[dev].tab, st, status, nullptr, 1, nullptr, kpw);
             tim_end(st);
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
             a.ssig = sig_s;

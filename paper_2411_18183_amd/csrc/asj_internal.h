@@ -302,10 +302,12 @@ hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
 // receives the high word (components 3, 4).
 // prep (may be NULL): the batch's slot fill and window maps, written by the
 // kernel's blocks before they sign (one launch fewer per batch).
+// kpw: keys per signing window (1 .. 64; fewer for long keys, see sign.hip).
 struct asj_batch_prep;
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
                            int grid_cap, hipStream_t st, const int32_t *status = nullptr,
-                           uint32_t *out_hi = nullptr, int stride = 1, const asj_batch_prep *prep = nullptr);
+                           uint32_t *out_hi = nullptr, int stride = 1, const asj_batch_prep *prep = nullptr,
+                           int kpw = ASJ_WAVE);
 // Sets *status = ASJ_EINVAL unless off[0] >= 0 and off[] never decreases.
 hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, hipStream_t st);
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);

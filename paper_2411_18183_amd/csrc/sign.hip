@@ -12,14 +12,17 @@ constexpr int kWaves = kBlock / ASJ_WAVE;
 
 // out[k * stride] = signature of key k (its low word with four GF(2^16)
 // components, whose high word goes to out_hi[k * stride]).  With has_prep
-// the blocks first do their part of a batch's preparation.
+// the blocks first do their part of a batch's preparation.  A wave signs
+// windows of kpw consecutive keys (1 .. 64): long keys fill a window's
+// passes with few keys, and fewer keys per window give few long keys
+// enough windows to occupy every compute unit.
 template <int MODE, int NSYM>
 __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
                                                       const int64_t *__restrict__ off, int64_t n,
                                                       uint32_t *__restrict__ out, uint32_t *__restrict__ out_hi,
                                                       int stride, const uint16_t *__restrict__ gtab,
                                                       const int32_t *__restrict__ status, asj_batch_prep prep,
-                                                      int has_prep)
+                                                      int has_prep, int kpw)
 {
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
     if (has_prep) asj_batch_prep_run(prep, blockIdx.x, gridDim.x, threadIdx.x, kBlock);
@@ -34,20 +37,21 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
 
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
-    const int64_t nwin = (n + ASJ_WAVE - 1) / ASJ_WAVE;
+    const int64_t nwin = (n + kpw - 1) / kpw;
     const int64_t end = off[n]; // the keys' bytes end here
     for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
-        const int64_t k = w * ASJ_WAVE + lane;
+        const int64_t k = w * kpw + lane;
+        const bool mine = lane < kpw && k < n;
         int64_t s = 0;
         int len = 0;
-        if (k < n) {
+        if (mine) {
             s = off[k];
             len = (int)(off[k + 1] - s);
         }
         uint32_t hi = 0;
         const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, end, kst[wave], kex[wave], kacc[wave], kown[wave], tab,
                                                         kacc2[kHi ? wave : 0], hi);
-        if (k < n) {
+        if (mine) {
             out[k * stride] = v;
             if (kHi) out_hi[k * stride] = hi;
         }
@@ -56,15 +60,15 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
 
 template <int MODE, int NSYM>
 hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride, const uint16_t *tab, int grid_cap,
-                  const int32_t *status, const asj_batch_prep *prep, hipStream_t st)
+                  const int32_t *status, const asj_batch_prep *prep, int kpw, hipStream_t st)
 {
     const asj_batch_prep none = {};
-    const int64_t nwin = (k->n + ASJ_WAVE - 1) / ASJ_WAVE;
+    const int64_t nwin = (k->n + kpw - 1) / kpw;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((sign_kernel<MODE, NSYM>), dim3((unsigned)blocks), dim3(kBlock), 0, st, k->data, k->offsets,
-                       k->n, out, out_hi, stride, tab, status, prep ? *prep : none, prep ? 1 : 0);
+                       k->n, out, out_hi, stride, tab, status, prep ? *prep : none, prep ? 1 : 0, kpw);
     return hipGetLastError();
 }
 
@@ -72,22 +76,23 @@ hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride
 
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab, int grid_cap,
                            hipStream_t st, const int32_t *status, uint32_t *out_hi, int stride,
-                           const asj_batch_prep *prep)
+                           const asj_batch_prep *prep, int kpw)
 {
     if (k->n == 0) return prep ? asj_launch_batch_prep(prep, st) : hipSuccess;
     if (stride < 1) return hipErrorInvalidValue;
+    if (kpw < 1 || kpw > ASJ_WAVE) kpw = ASJ_WAVE;
     if (mode == ASJ_MODE_SIG16 && nsym == 4) {
         if (!out_hi) return hipErrorInvalidValue;
-        return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, prep, st);
+        return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, prep, kpw, st);
     }
     if (mode == ASJ_MODE_SIG16 && nsym == 2)
-        return launch<ASJ_MODE_SIG16, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
+        return launch<ASJ_MODE_SIG16, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, kpw, st);
     if (mode == ASJ_MODE_SIG16 && nsym == 1)
-        return launch<ASJ_MODE_SIG16, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
+        return launch<ASJ_MODE_SIG16, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, kpw, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 4)
-        return launch<ASJ_MODE_SIG8, 4>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
+        return launch<ASJ_MODE_SIG8, 4>(k, out, nullptr, stride, tab, grid_cap, status, prep, kpw, st);
     if (mode == ASJ_MODE_SIG8 && nsym == 2)
-        return launch<ASJ_MODE_SIG8, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
-    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, st);
+        return launch<ASJ_MODE_SIG8, 2>(k, out, nullptr, stride, tab, grid_cap, status, prep, kpw, st);
+    if (mode == ASJ_MODE_PLAIN) return launch<ASJ_MODE_PLAIN, 1>(k, out, nullptr, stride, tab, grid_cap, status, prep, kpw, st);
     return hipErrorInvalidValue;
 }

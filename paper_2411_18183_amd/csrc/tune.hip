@@ -46,7 +46,9 @@ Key make_key(int batch, int64_t n_build, const asj_opts &o)
 }
 
 constexpr float kLoadFactors[] = {0.25f, 0.35f, 0.5f, 0.7f};
-constexpr int kKeysPerWindow[] = {16, 32, 64};
+// few keys per window for long keys: 131k keys of 4 KB in windows of 64 give
+// one block per compute unit
+constexpr int kKeysPerWindow[] = {4, 8, 16, 32, 64};
 constexpr int kGridRounds[] = {1, 2, 4};
 constexpr int kReps = 3;
 

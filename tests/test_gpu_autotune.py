@@ -41,8 +41,8 @@ def test_autotune_single_join(A, oracle, wl):
     want = oracle.join_hash(w.R, w.S)
     try:
         res = A.autotune(Rk, Sk, out, cnt)
-        assert res["trials"] >= 36 and res["best_ms"] <= res["default_ms"]
-        assert res["load_factor"] in (0.25, 0.35, 0.5, 0.7) and res["keys_per_window"] in (16, 32, 64)
+        assert res["trials"] >= 60 and res["best_ms"] <= res["default_ms"]
+        assert res["load_factor"] in (0.25, 0.35, 0.5, 0.7) and res["keys_per_window"] in (4, 8, 16, 32, 64)
         assert res["grid_rounds"] in (1, 2, 4)
         assert int(cnt[0]) == len(want)  # the trial joins were exact too
         t = A.asj_build(Rk)  # options left to the library
@@ -71,7 +71,7 @@ def test_autotune_batch(A, oracle, wl):
     cnt = torch.zeros(b.njoins, dtype=torch.int64, device="cuda")
     try:
         res = A.autotune_batch(R, S, dev(b.r_seg), dev(b.s_seg), out, dev(oseg), cnt)
-        assert res["trials"] == 72 and res["best_ms"] <= res["default_ms"]  # 4 x 3 x 2 schedules x 3 grids
+        assert res["trials"] == 120 and res["best_ms"] <= res["default_ms"]  # 4 x 5 x 2 schedules x 3 grids
         assert res["grid_rounds"] in (1, 2, 4)
         got, gseg, counts, _, _ = A.join_batch(R, S, b.r_seg, b.s_seg)  # options left to the library
         outh = got.cpu().numpy()

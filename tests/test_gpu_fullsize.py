@@ -54,7 +54,8 @@ def gpu_signatures(A, keys):
 # Probe configurations the autotuner may choose for a single join with a
 # device-memory table (load factor, keys per window, grid rounds, schedule),
 # beside the library defaults and the autotuner's own choice.
-BENCH_CONFIGS = ([dict(load_factor=0.25, keys_per_window=k, grid_rounds=g) for k in (16, 32, 64) for g in (1, 2, 4)]
+BENCH_CONFIGS = ([dict(load_factor=0.25, keys_per_window=k, grid_rounds=g) for k in (4, 8, 16, 32, 64)
+                  for g in (1, 2, 4)]
                  + [dict(load_factor=lf, keys_per_window=32, grid_rounds=1) for lf in (0.35, 0.5, 0.7)]
                  + [dict(load_factor=0.25, keys_per_window=32, grid_rounds=1, split=True)])
 
