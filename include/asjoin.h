@@ -381,7 +381,7 @@ typedef struct asj_tune_result {
 /* Autotuner for asj_join: times whole joins of r and s (one untimed and
  * three timed calls per configuration, median, HIP events on `stream`) over
  * the load factors {0.25, 0.35, 0.5, 0.7} that give distinct capacities,
- * keys_per_window {16, 32, 64}, both probe schedules and grid_rounds
+ * keys_per_window {4, 8, 16, 32, 64}, both probe schedules and grid_rounds
  * {1, 2, 4}, with the signature parameters and ASJ_PLAIN / ASJ_NO_VERIFY /
  * ASJ_FINGERPRINT flags of `opts` (NULL = defaults; its load factor, keys
  * per window, grid rounds and schedule are ignored), and records the
@@ -418,7 +418,11 @@ typedef struct asj_server asj_server;
 typedef struct asj_server_opts {
     int32_t slots;              /* concurrent launches (HIP streams); <= 0 means 4 */
     int64_t hbm_budget;         /* device bytes admitted requests may hold; <= 0 means 200 GiB */
-    int64_t max_batch_keys;     /* probe keys packed into one launch; <= 0 means 4Mi */
+    int64_t max_batch_keys;     /* probe keys packed into one launch (a request larger than this
+                                   still gets a launch of its own); <= 0 means 256Ki: requests are
+                                   bound by their host-to-device copies, so packing large requests
+                                   gains no throughput and a request completes only when its whole
+                                   launch does */
     int32_t max_batch_requests; /* requests packed into one launch; <= 0 means 256 (1 = no packing) */
     int32_t dry_run;            /* nonzero: no device work; a launch completes after dry_ns_per_key
                                    nanoseconds per probe key (exercises the scheduler without a GPU;
@@ -435,6 +439,9 @@ typedef struct asj_request_info {
     double t_done_ms;       /* results in the caller's buffer */
     int32_t batch_id;       /* launch sequence number */
     int32_t batch_requests; /* requests packed into that launch */
+    double t_device_ms;     /* device time of that launch (HIP events): its input copies, kernel
+                               and output copies */
+    double t_kernel_ms;     /* the launch's probe kernel alone */
 } asj_request_info;
 
 typedef struct asj_server_stats_t {

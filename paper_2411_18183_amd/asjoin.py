@@ -530,7 +530,8 @@ class asj_server_opts(ctypes.Structure):
 class asj_request_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("count", ctypes.c_int64), ("t_arrive_ms", ctypes.c_double),
                 ("t_launch_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double), ("batch_id", ctypes.c_int32),
-                ("batch_requests", ctypes.c_int32)]
+                ("batch_requests", ctypes.c_int32), ("t_device_ms", ctypes.c_double),
+                ("t_kernel_ms", ctypes.c_double)]
 
 
 class asj_server_stats_t(ctypes.Structure):
@@ -610,7 +611,8 @@ class Server:
             self._live.pop(ticket, None)
         return {"status": rc, "count": int(info.count), "t_arrive_ms": info.t_arrive_ms,
                 "t_launch_ms": info.t_launch_ms, "t_done_ms": info.t_done_ms, "batch_id": info.batch_id,
-                "batch_requests": info.batch_requests}
+                "batch_requests": info.batch_requests, "t_device_ms": info.t_device_ms,
+                "t_kernel_ms": info.t_kernel_ms}
 
     def stats(self) -> dict:
         st = asj_server_stats_t()

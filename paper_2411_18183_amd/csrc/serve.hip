@@ -47,11 +47,15 @@ struct Req {
     bool done = false;
     bool claimed = false; // a caller waits on this ticket (one waiter per ticket)
     int batch_id = -1, batch_n = 0;
+    double dev_ms = 0, kern_ms = 0; // device time of its launch: copies and kernel, kernel alone
 };
 
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
+    // timing events of the launch: before its input copies, around its
+    // kernel, after its output copies
+    hipEvent_t t_in = nullptr, t_k0 = nullptr, t_k1 = nullptr, t_out = nullptr;
     bool busy = false;
     std::vector<Req *> reqs;
     uint8_t *pin = nullptr; // pinned staging: metadata up, counts down
@@ -199,6 +203,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
     uint8_t *d = nullptr;
     hipError_t e = hipMallocAsync((void **)&d, dev_bytes, sl.st);
     if (e != hipSuccess) return ASJ_ENOMEM;
+    e = hipEventRecord(sl.t_in, sl.st);
     db = 0;
     for (int j = 0; j < J && e == hipSuccess; j++) {
         const Req *r = batch[j];
@@ -241,10 +246,12 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         if (S->tbl.split && K > 0) {
             const asj_keys keys = {a.sdata, a.soff, a.sids, K};
             e = asj_launch_sign(mode, S->tbl.plain ? 1 : S->tbl.sig.nsym, &keys, (uint32_t *)(d + o_ssig), S->tab,
-                                256 * 16, sl.st);
+                                256 * 16, sl.st, nullptr, nullptr, 1, nullptr, S->tbl.keys_per_window);
             a.ssig = (const uint32_t *)(d + o_ssig);
         }
+        if (e == hipSuccess) e = hipEventRecord(sl.t_k0, sl.st);
         if (e == hipSuccess) e = asj_launch_probe(&a, mode, S->tbl.sig.nsym, S->tab, 256 * 16, sl.st);
+        if (e == hipSuccess) e = hipEventRecord(sl.t_k1, sl.st);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.pin + sl.counts_off, d + o_cnt, 8 * (size_t)J, hipMemcpyDeviceToHost, sl.st);
@@ -255,6 +262,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
             e = hipMemcpyAsync(r->out, d + o_out + 8 * (size_t)ob, 8 * (size_t)r->cap, hipMemcpyDeviceToHost, sl.st);
         ob += r->cap;
     }
+    if (e == hipSuccess) e = hipEventRecord(sl.t_out, sl.st);
     if (e == hipSuccess) e = hipEventRecord(sl.ev, sl.st);
     (void)hipFreeAsync(d, sl.st);
     return e == hipSuccess ? ASJ_OK : ASJ_EHIP;
@@ -270,8 +278,15 @@ bool slot_done(asj_server *S, Slot &sl)
 void finish_slot(asj_server *S, Slot &sl, int status)
 {
     const double t = S->now_ms();
+    float dev_ms = 0.0f, kern_ms = 0.0f;
+    if (!S->o.dry_run && status == ASJ_OK) {
+        if (hipEventElapsedTime(&dev_ms, sl.t_in, sl.t_out) != hipSuccess) dev_ms = -1.0f;
+        if (hipEventElapsedTime(&kern_ms, sl.t_k0, sl.t_k1) != hipSuccess) kern_ms = -1.0f;
+    }
     for (size_t j = 0; j < sl.reqs.size(); j++) {
         Req *r = sl.reqs[j];
+        r->dev_ms = dev_ms;
+        r->kern_ms = kern_ms;
         if (!S->o.dry_run && status == ASJ_OK) r->count = ((const int64_t *)(sl.pin + sl.counts_off))[j];
         r->status = status;
         r->t_done = t;
@@ -367,7 +382,7 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
     if (t && asj_kind_marks_build(t->kind)) return ASJ_EUNSUPPORTED; // right / full outer: per-call build marks
     if (o.slots <= 0) o.slots = 4;
     if (o.hbm_budget <= 0) o.hbm_budget = 200ll << 30;
-    if (o.max_batch_keys <= 0) o.max_batch_keys = 4ll << 20;
+    if (o.max_batch_keys <= 0) o.max_batch_keys = 256ll << 10;
     if (o.max_batch_requests <= 0) o.max_batch_requests = 256;
     if (o.slots > 64) return ASJ_EINVAL;
     asj_server *S = new (std::nothrow) asj_server();
@@ -384,9 +399,14 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
         }
         for (Slot &sl : S->slots) {
             if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+                hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.t_in, hipEventDisableSystemFence) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.t_k0, hipEventDisableSystemFence) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.t_k1, hipEventDisableSystemFence) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.t_out, hipEventDisableSystemFence) != hipSuccess) {
                 for (Slot &x : S->slots) {
-                    if (x.ev) (void)hipEventDestroy(x.ev);
+                    for (hipEvent_t ev : {x.ev, x.t_in, x.t_k0, x.t_k1, x.t_out})
+                        if (ev) (void)hipEventDestroy(ev);
                     if (x.st) (void)hipStreamDestroy(x.st);
                 }
                 delete S;
@@ -401,7 +421,7 @@ int asj_server_create(const asj_table *t, const asj_server_opts *opts, asj_serve
             if (grow_staging(sl, full) != ASJ_OK) {
                 for (Slot &x : S->slots) {
                     if (x.pin) (void)hipHostFree(x.pin);
-                    (void)hipEventDestroy(x.ev);
+                    for (hipEvent_t ev : {x.ev, x.t_in, x.t_k0, x.t_k1, x.t_out}) (void)hipEventDestroy(ev);
                     (void)hipStreamDestroy(x.st);
                 }
                 delete S;
@@ -468,6 +488,8 @@ int asj_server_wait(asj_server *S, int64_t ticket, asj_request_info *info)
         info->t_done_ms = r->t_done;
         info->batch_id = r->batch_id;
         info->batch_requests = r->batch_n;
+        info->t_device_ms = r->dev_ms;
+        info->t_kernel_ms = r->kern_ms;
     }
     const int st = r->status;
     S->reqs.erase(ticket);
@@ -501,7 +523,8 @@ int asj_server_destroy(asj_server *S)
     if (S->th.joinable()) S->th.join();
     for (Slot &sl : S->slots) {
         if (sl.pin) (void)hipHostFree(sl.pin);
-        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        for (hipEvent_t ev : {sl.ev, sl.t_in, sl.t_k0, sl.t_k1, sl.t_out})
+            if (ev) (void)hipEventDestroy(ev);
         if (sl.st) (void)hipStreamDestroy(sl.st);
     }
     for (auto &kv : S->reqs) delete kv.second;

@@ -44,6 +44,8 @@ def test_results_identical_alone_and_in_the_mix(A, oracle, wl, sched):
     tickets = [srv.submit(*b) for b in bufs]
     infos = [srv.wait(x) for x in tickets]
     assert max(i["batch_requests"] for i in infos) > 1, "nothing was batched"
+    # device time of each request's launch (HIP events): the kernel is part of it
+    assert all(0 < i["t_kernel_ms"] <= i["t_device_ms"] for i in infos)
     for k, (info, b) in enumerate(zip(infos, bufs)):
         got = oracle.sort_pairs(b[2][:info["count"]].numpy())
         assert info["status"] == 0
