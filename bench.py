@@ -62,15 +62,17 @@ def parse():
     ap.add_argument("--cpu-scale", type=float, default=0.25, help="size of the CPU oracle sample relative to the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain hash join comparison")
-    ap.add_argument("--batch-scale", type=float, default=0.25,
+    ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="size of the 256-join batch workload run beside the main line (0 = skip)")
+    ap.add_argument("--dna-scale", type=float, default=1.0,
+                    help="size of the DNA join run beside the main line (0 = skip)")
     ap.add_argument("--tiny-instances", type=int, default=128,
                     help="independent tiny joins run as one batch beside the main line (0 = skip)")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="size of the resident build side of the serving run (1.0 = 10M keys; 0 = skip)")
-    ap.add_argument("--serve-arrivals", type=int, default=48)
-    ap.add_argument("--length-sweep", action="store_true",
-                    help="also time signature vs plain joins on keys of one length, 4 B .. 4 KB")
+    ap.add_argument("--serve-arrivals", type=int, default=400)
+    ap.add_argument("--sweep-lengths", default="2,8,64,512,4096",
+                    help="key lengths (bytes, comma-separated) of the signature vs plain join sweep ('' = skip)")
     ap.add_argument("--host-budget", type=int, default=1 << 30, metavar="BYTES",
                     help="device budget of the partitioned host-memory join (0: skip the host-memory joins)")
     ap.add_argument("--no-variants", action="store_true", help="skip the signature-width comparison")
@@ -370,24 +372,32 @@ def bench_tiny_latency(A, torch, W, runs: int = 1000):
             "workload": "one tiny join (R = S = 10k keys of 256 B, 2000 matches) per call, inputs resident"}
 
 
-def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096),
-                       probe_bytes: int = 1 << 29):
+def bench_length_sweep(A, torch, W, steps: int, lengths=(2, 8, 64, 512, 4096), probe_bytes: int = 1 << 29,
+                       autotune: bool = True):
     """Signature join vs plain byte-compare hash join (and the fingerprint
-    control: the plain join's key hash stored and compared) on keys of one length
-    (R = |S| / 4, 20% of S copies R rows, bytes uniform over all 256 values;
-    |S| = min(4M, probe_bytes / length)), both with the same fixed options
-    (load factor 0.5, 64 keys per window, fused schedule)."""
+    control: the plain join's key hash stored and compared) on keys of one
+    length: |S| = min(4M, probe_bytes / length), R = |S| / 4 keys, but at most
+    a quarter of the 256^length possible keys (2-byte keys: 16384), 20% of S
+    copy R rows, bytes uniform over all 256 values.  Each method runs with the
+    options its own autotuning picked on these inputs (else the defaults)."""
     rows = []
     for L in lengths:
         n = int(min(4_000_000, probe_bytes // L))
-        w = W.fixed_length(seed=20, m=n // 4, n=n, key_len=L)
+        m = int(min(n // 4, 256 ** min(L, 4) // 4))
+        w = W.fixed_length(seed=20, m=m, n=n, key_len=L)
         Rk, Sk = A.DeviceKeys.from_host(w.R), A.DeviceKeys.from_host(w.S)
-        out = torch.empty((n + n // 4, 2), dtype=torch.int32, device="cuda")
-        res = {"key_len": L, "R": w.R.n, "S": n}
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        A.asj_join(Rk, Sk, torch.empty((0, 2), dtype=torch.int32, device="cuda"), cnt)  # |T| first
+        total = int(cnt[0])
+        out = torch.empty((total + 1024, 2), dtype=torch.int32, device="cuda")
+        res = {"key_len": L, "R": w.R.n, "S": n, "pairs": total}
         for name, flags in (("signature", 0), ("plain", A.ASJ_PLAIN), ("fingerprint", A.ASJ_FINGERPRINT)):
             cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
-            fl = flags | A.ASJ_PROBE_FUSED
-            run = lambda: A.asj_join(Rk, Sk, out, cnt, load_factor=0.5, keys_per_window=64, flags=fl)
+            if autotune:
+                t = A.autotune(Rk, Sk, out, cnt, flags=flags)
+                res[f"options_{name}"] = {k: t[k] for k in ("load_factor", "keys_per_window", "grid_rounds",
+                                                             "schedule")}
+            run = lambda: A.asj_join(Rk, Sk, out, cnt, flags=flags)
             run()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -396,11 +406,12 @@ def bench_length_sweep(A, torch, W, steps: int, lengths=(4, 8, 16, 32, 64, 128, 
             torch.cuda.synchronize()
             res[f"ms_{name}"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
             res[f"pairs_{name}"] = int(cnt[0])
-        assert res["pairs_signature"] == res["pairs_plain"] == res["pairs_fingerprint"], res
+        assert res["pairs_signature"] == res["pairs_plain"] == res["pairs_fingerprint"] == total, res
         res["signature_join_speedup"] = round(res["ms_plain"] / res["ms_signature"], 3)
         log(f"length sweep: {res}")
         rows.append(res)
         del Rk, Sk, out, w
+        A.autotune_clear()
     return rows
 
 
@@ -440,7 +451,16 @@ def bench_host(A, torch, w, expected: int, budget: int, Sk, runs: int = 2):
 
 
 def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, seed: int = 5):
-    """Continuous-batching server over a resident build table, Poisson arrivals."""
+    """Continuous-batching server over a resident build table, Poisson arrivals.
+
+    Every load point submits `arrivals` requests (open loop: a request is
+    submitted at its arrival time whatever the server's state) while a waiter
+    thread collects them in order; output buffers rotate through a pool, so a
+    request waits for the one submitted `pool` requests before it only when
+    that many are outstanding.  Latency = completion - submission on the
+    server's clock; the device time of each request's launch (its copies and
+    kernel, HIP events) is reported beside it."""
+    import threading
     import numpy as np
     t = time.perf_counter()
     R = W.served_build_side(seed=seed, scale=scale)
@@ -449,58 +469,79 @@ def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, see
     payloads = [W.served_request(R, seed=seed, request=i) for i in range(n_payloads)]
     pins = [(torch.from_numpy(q.data).pin_memory(), torch.from_numpy(q.offsets).pin_memory()) for q in payloads]
     nmax = max(q.n for q in payloads)
-    outs = [torch.empty((nmax, 2), dtype=torch.int32).pin_memory() for _ in range(arrivals)]
+    pool = min(arrivals, 64)
+    outs = [torch.empty((nmax, 2), dtype=torch.int32).pin_memory() for _ in range(pool)]
     torch.cuda.synchronize()
     log(f"serving: R={R.n} payloads={n_payloads} keys={sum(q.n for q in payloads)} "
         f"bytes={sum(q.nbytes for q in payloads)} prepared in {time.perf_counter() - t:.1f}s")
-    expect = None
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)), 3)
 
     def run(srv, rate_per_s=None, count=arrivals):
         order = [i % n_payloads for i in range(count)]
         times = W.poisson_arrivals(seed + 100, rate_per_s, count) if rate_per_s else np.zeros(count)
-        tickets = []
+        tickets, infos = [None] * count, [None] * count
+        done = [threading.Event() for _ in range(count)]
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(count):
+                ready.acquire()
+                infos[i] = srv.wait(tickets[i])
+                done[i].set()
+        th = threading.Thread(target=waiter)
+        th.start()
         t0 = time.perf_counter()
         for i, p in enumerate(order):
-            while time.perf_counter() - t0 < times[i]:
-                pass
+            while True:
+                left = times[i] - (time.perf_counter() - t0)
+                if left <= 0:
+                    break
+                if left > 2e-3:
+                    time.sleep(left - 1e-3)
+            if i >= pool:
+                done[i - pool].wait()  # its output buffer is free again
             d, o = pins[p]
-            tickets.append(srv.submit(d, o, outs[i][:payloads[p].n]))
-        infos = [srv.wait(x) for x in tickets]
+            tickets[i] = srv.submit(d, o, outs[i % pool][:payloads[p].n])
+            ready.release()
+        th.join()
         lat = np.array([x["t_done_ms"] - x["t_arrive_ms"] for x in infos])
+        queue = np.array([x["t_launch_ms"] - x["t_arrive_ms"] for x in infos])
+        dev = np.array([x["t_device_ms"] for x in infos])
+        kern = np.array([x["t_kernel_ms"] for x in infos])
         span = max(x["t_done_ms"] for x in infos) - min(x["t_arrive_ms"] for x in infos)
         counts = [x["count"] for x in infos]
         assert all(x["status"] == 0 for x in infos)
-        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        return {"arrivals": count, "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                "queue_p50_ms": pct(queue, 50), "device_p50_ms": pct(dev, 50), "device_p99_ms": pct(dev, 99),
+                "kernel_p50_ms": pct(kern, 50), "kernel_p99_ms": pct(kern, 99),
                 "throughput_req_s": round(count / (span * 1e-3), 1),
                 "probe_tuples_s": round(sum(payloads[p].n for p in order) / (span * 1e-3), 1),
                 "mean_batch": round(float(np.mean([x["batch_requests"] for x in infos])), 2)}, order, counts
 
-    # each server is warmed with one full saturation pass (device pool and
-    # pinned staging reach their working size) before anything is timed
+    # each server is warmed with one pass (device pool and pinned staging
+    # reach their working size) before anything is timed
     serial = A.Server(table, slots=1, max_batch_requests=1)
-    run(serial)
+    run(serial, count=2 * n_payloads)
     sat_serial, order, counts = run(serial)
-    serial.close()
     expect = {p: c for p, c in zip(order, counts)}
     cb = A.Server(table, slots=4)
-    run(cb)
+    run(cb, count=2 * n_payloads)
     sat_cb, order, counts = run(cb)
     assert all(expect[p] == c for p, c in zip(order, counts)), "results differ between servers"
-    mu = sat_cb["throughput_req_s"]
-    sweep = []
+    mu = max(sat_cb["throughput_req_s"], sat_serial["throughput_req_s"])
+    sweep, serial_sweep = [], []
     for f in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1):
-        res, order, counts = run(cb, rate_per_s=f * mu)
-        assert all(expect[p] == c for p, c in zip(order, counts))
-        res["load"] = f
-        res["rate_req_s"] = round(f * mu, 1)
-        sweep.append(res)
+        for srv, dst in ((cb, sweep), (serial, serial_sweep)):
+            res, order, counts = run(srv, rate_per_s=f * mu)
+            assert all(expect[p] == c for p, c in zip(order, counts))
+            res["load"] = f
+            res["rate_req_s"] = round(f * mu, 1)
+            dst.append(res)
+        log(f"serving load {f}: continuous p50/p99 {sweep[-1]['p50_ms']}/{sweep[-1]['p99_ms']} ms, "
+            f"serial {serial_sweep[-1]['p50_ms']}/{serial_sweep[-1]['p99_ms']} ms")
     cb.close()
-    serial = A.Server(table, slots=1, max_batch_requests=1)
-    serial_sweep = []
-    for f in (0.5, 0.9):
-        res, order, counts = run(serial, rate_per_s=f * mu)
-        res["load"] = f
-        serial_sweep.append(res)
     serial.close()
     need = [q.nbytes + 26 * q.n + (1 << 13) for q in payloads]  # a request's device footprint, rounded up
     small_budget = int(max(2.0 * float(np.mean(need)), 1.1 * max(need)))
@@ -515,7 +556,103 @@ def bench_serving(A, torch, W, scale: float, n_payloads: int, arrivals: int, see
                         f"10k-1M keys (30% copies of R rows, 70% fresh 64-1024 B); {arrivals} arrivals per point",
             "saturation_serial": sat_serial, "saturation_continuous": sat_cb, "sweep_continuous": sweep,
             "sweep_serial": serial_sweep, "small_budget": small,
-            "note": "latency = completion (results in pinned host memory) - submission, host-to-device copies included"}
+            "continuous_p50_le_serial_every_load": all(c["p50_ms"] <= s_["p50_ms"]
+                                                       for c, s_ in zip(sweep, serial_sweep)),
+            "note": "latency = completion (results in pinned host memory) - submission, host-to-device copies "
+                    "included; device = the request's launch on the device (input copies, kernel, output copies); "
+                    "saturation = all arrivals at once; load points at fractions of the faster saturation rate"}
+
+
+def measure_single(A, torch, W, name: str, seed: int, scale: float, steps: int, warmup: int, autotune: bool,
+                   plain_too: bool = True, traffic_ok=None):
+    """One workload's single join through asj_join: the step time, per-kernel
+    times (HIP events on the call's stream), the dominant kernel's roofline
+    from its compulsory bytes, and the plain byte-compare hash join and the
+    fingerprint control on the same inputs and GPU.  Returns (result dict,
+    handles for later measurements)."""
+    import numpy as np
+    t = time.perf_counter()
+    w = getattr(W, name)(seed=seed, scale=scale)
+    log(f"generated {name} R={w.R.n} S={w.S.n} bytes={w.R.nbytes + w.S.nbytes} in {time.perf_counter() - t:.1f}s")
+    Rk = A.DeviceKeys.from_host(w.R)
+    Sk = A.DeviceKeys.from_host(w.S)
+    torch.cuda.synchronize()
+    expected = int(w.meta["expected_matches"])
+    cap = expected + 1024
+    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    # the autotuner times whole joins over its grid on these inputs (setup, not
+    # timed); the timed joins leave the options to the library, which uses its choice
+    tune = A.autotune(Rk, Sk, out, counts) if autotune else None
+    if tune:
+        log(f"{name} autotune: {tune}")
+    lf = tune["load_factor"] if tune else 0.5
+    for _ in range(max(1, warmup)):
+        A.asj_join(Rk, Sk, out, counts)
+    torch.cuda.synchronize()
+    n_pairs, n_cand = (int(x) for x in counts.tolist())
+    if n_pairs > cap:
+        out = torch.empty((n_pairs, 2), dtype=torch.int32, device="cuda")
+        A.asj_join(Rk, Sk, out, counts)
+        torch.cuda.synchronize()
+    pairs = out[:n_pairs].cpu().numpy()
+    r_len = w.R.lengths()
+    verify_bytes = int(r_len[pairs[:, 0]].sum()) if n_pairs else 0
+    log(f"{name}: |T|={n_pairs} candidates={n_cand} (expected |T|={expected})")
+
+    ms_step, phase_ms, _ = run_steps(A, torch, Rk, Sk, out, counts, steps)
+    check = int(counts[0])
+    log(f"{name} signature join: {ms_step:.3f} ms/step; phases {phase_ms}")
+    tab_cap = 64
+    while tab_cap * lf < w.R.n:
+        tab_cap <<= 1
+    slots_per_key = expected_slots(w.R.n, tab_cap, n_pairs / max(1, w.S.n))
+    nbytes = {
+        "sign_build": algorithmic_bytes("sign_build", w.R.n, w.R.nbytes, tab_cap, 0),
+        "sign_probe_verify": algorithmic_bytes("sign_probe_verify", w.S.n, w.S.nbytes, tab_cap, n_pairs,
+                                               slots_per_key),
+        "table_init": algorithmic_bytes("table_init", 0, 0, tab_cap, 0),
+        "insert": algorithmic_bytes("insert", w.R.n, 0, tab_cap, 0),
+    }
+    dominant = max(phase_ms, key=lambda k: phase_ms[k])
+    dom_bytes = nbytes.get(dominant, 0)
+    achieved = dom_bytes / (phase_ms[dominant] * 1e-3) / 1e9
+    traffic = traffic_ok(name, dominant) if traffic_ok else None
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "algorithmic_bytes": dom_bytes, "avg_ms": round(phase_ms[dominant], 4),
+                "verify_bytes": 2 * verify_bytes if dominant.endswith("probe_verify") else 0,
+                "slots_per_probe_key": round(slots_per_key, 3)}
+    if traffic:
+        roofline["traffic_gbps"] = round(traffic / (phase_ms[dominant] * 1e-3) / 1e9, 1)
+    # whole-step compulsory bytes: both arenas once, offsets, ids, signatures, table, output
+    step_bytes = (w.R.nbytes + w.S.nbytes + 8 * (w.R.n + 1) + 8 * (w.S.n + 1) + 4 * w.R.n + 4 * w.S.n
+                  + 8 * tab_cap + 8 * w.R.n + 8 * w.S.n + 8 * n_pairs)
+    step_gbps = step_bytes / (ms_step * 1e-3) / 1e9
+    res = {"R": w.R.n, "S": w.S.n, "key_bytes": int(w.R.nbytes + w.S.nbytes), "pairs": n_pairs,
+           "candidates": n_cand, "pairs_match_expected": n_pairs == expected and check == n_pairs,
+           "ms_per_step": round(ms_step, 4), "value": round(w.S.n / (ms_step * 1e-3), 1), "unit": "probe tuples/s",
+           "key_gbps": round((w.R.nbytes + w.S.nbytes) / (ms_step * 1e-3) / 1e9, 1),
+           "hbm_gbps_step": round(step_gbps, 1), "frac_peak_step": round(step_gbps / HBM_PEAK_GBPS, 4),
+           "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()}, "roofline": roofline, "autotune": tune}
+    if plain_too:
+        counts_p = torch.zeros(2, dtype=torch.int64, device="cuda")
+        for label, flags in (("plain_hash_join", A.ASJ_PLAIN), ("fingerprint_control", A.ASJ_FINGERPRINT)):
+            tune_p = A.autotune(Rk, Sk, out, counts_p, flags=flags) if autotune else None
+            for _ in range(max(1, warmup)):
+                A.asj_join(Rk, Sk, out, counts_p, flags=flags)
+            ms_p, phase_p, _ = run_steps(A, torch, Rk, Sk, out, counts_p, steps, flags=flags)
+            assert int(counts_p[0]) == n_pairs, f"{label} disagrees on |T|"
+            res[label] = {"ms_per_step": round(ms_p, 4), "value": round(w.S.n / (ms_p * 1e-3), 1),
+                          "unit": "probe tuples/s", "compared": int(counts_p[1]),
+                          "phases_ms": {k: round(v, 4) for k, v in phase_p.items()},
+                          "signature_join_speedup": round(ms_p / ms_step, 3), "autotune": tune_p}
+            log(f"{name} {label}: {ms_p:.3f} ms/step")
+        res["fingerprint_control"]["note"] = "compared = signature-equal candidates (fingerprint-equal here)"
+        res["plain_hash_join"]["note"] = "compared = occupied slots whose keys were compared"
+    handles = {"w": w, "Rk": Rk, "Sk": Sk, "out": out, "counts": counts, "lf": lf, "n_pairs": n_pairs,
+               "expected": expected}
+    return res, handles
 
 
 def main():
@@ -539,77 +676,28 @@ def main():
     torch.cuda.set_device(0)
     A.lib()
 
-    seed = args.seed if args.seed is not None else {"large": 2, "tiny": 1, "dna": 3}[args.workload]
-    t = time.perf_counter()
-    w = getattr(W, args.workload)(seed=seed, scale=args.scale)
-    log(f"generated {args.workload} R={w.R.n} S={w.S.n} bytes={w.R.nbytes + w.S.nbytes} in {time.perf_counter() - t:.1f}s")
-    Rk = A.DeviceKeys.from_host(w.R)
-    Sk = A.DeviceKeys.from_host(w.S)
-    torch.cuda.synchronize()
-
-    expected = int(w.meta["expected_matches"])
-    cap = expected + 1024
-    out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
-    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
-
-    # the autotuner times whole joins over its grid on these inputs (setup, not
-    # timed); the timed joins leave the options to the library, which uses its choice
-    tune = None if args.no_autotune else A.autotune(Rk, Sk, out, counts)
-    if tune:
-        log(f"autotune: {tune}")
-    lf = tune["load_factor"] if tune else 0.5
-    # warmup (and the size of T)
-    for _ in range(max(1, args.warmup)):
-        A.asj_join(Rk, Sk, out, counts)
-    torch.cuda.synchronize()
-    n_pairs, n_cand = (int(x) for x in counts.tolist())
-    if n_pairs > cap:
-        out = torch.empty((n_pairs, 2), dtype=torch.int32, device="cuda")
-        A.asj_join(Rk, Sk, out, counts)
-        torch.cuda.synchronize()
-    pairs = out[:n_pairs].cpu().numpy()
-    s_len = w.S.lengths()
-    r_len = w.R.lengths()
-    verify_bytes = int(r_len[pairs[:, 0]].sum()) if n_pairs else 0
-    log(f"|T|={n_pairs} candidates={n_cand} (expected |T|={expected})")
-
-    ms_step, phase_ms, phase_calls = run_steps(A, torch, Rk, Sk, out, counts, args.steps)
-    check = int(counts[0])
-    log(f"signature join: {ms_step:.3f} ms/step; phases {phase_ms}")
-
-    tab_cap = 64
-    while tab_cap * lf < w.R.n:
-        tab_cap <<= 1
-    slots_per_key = expected_slots(w.R.n, tab_cap, n_pairs / max(1, w.S.n))
-    nbytes = {
-        "sign_build": algorithmic_bytes("sign_build", w.R.n, w.R.nbytes, tab_cap, 0),
-        "sign_probe_verify": algorithmic_bytes("sign_probe_verify", w.S.n, w.S.nbytes, tab_cap, n_pairs,
-                                               slots_per_key),
-        "table_init": algorithmic_bytes("table_init", 0, 0, tab_cap, 0),
-        "insert": algorithmic_bytes("insert", w.R.n, 0, tab_cap, 0),
-    }
-    dominant = max(phase_ms, key=lambda k: phase_ms[k])
-    dom_bytes = nbytes.get(dominant, 0)
-    achieved = dom_bytes / (phase_ms[dominant] * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    def traffic_ok(name, kernel):
+        """Measured bytes per launch of `kernel` on workload `name`, when the
+        counters were taken on the current kernel sources."""
+        if not os.path.exists(TRAFFIC_FILE):
+            return None
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            ent = tr.get("kernels", {}).get(dominant)
-            if tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == args.workload and ent:
-                traffic = int(ent["bytes_per_launch"])
+            ent = tr.get("kernels", {}).get(kernel)
+            if tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == name and ent:
+                return int(ent["bytes_per_launch"])
         except (OSError, ValueError, KeyError):
-            traffic = None
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "algorithmic_bytes": dom_bytes, "avg_ms": round(phase_ms[dominant], 4),
-                "verify_bytes": 2 * verify_bytes if dominant.endswith("probe_verify") else 0,
-                "slots_per_probe_key": round(slots_per_key, 3)}
+            pass
+        return None
 
-    # whole-step compulsory bytes: both arenas once, offsets, ids, signatures, table, output
-    step_bytes = (w.R.nbytes + w.S.nbytes + 8 * (w.R.n + 1) + 8 * (w.S.n + 1) + 4 * w.R.n + 4 * w.S.n
-                  + 8 * tab_cap + 8 * w.R.n + 8 * w.S.n + 8 * n_pairs)
-    step_gbps = step_bytes / (ms_step * 1e-3) / 1e9
+    seed = args.seed if args.seed is not None else {"large": 2, "tiny": 1, "dna": 3}[args.workload]
+    main_res, h = measure_single(A, torch, W, args.workload, seed, args.scale, args.steps, args.warmup,
+                                 not args.no_autotune, plain_too=not args.no_plain, traffic_ok=traffic_ok)
+    w, Rk, Sk, out, counts = h["w"], h["Rk"], h["Sk"], h["out"], h["counts"]
+    lf, n_pairs, expected = h["lf"], h["n_pairs"], h["expected"]
+    ms_step = main_res["ms_per_step"]
+    roofline = main_res["roofline"]
+    tune = main_res["autotune"]
 
     # the plain streaming read rate on this part (the library's read kernel
     # over the probe key arena, best of three grid sizes), so the roofline
@@ -630,35 +718,7 @@ def main():
             read_gbps, read_grid = gbps, grid
     roofline["stream_read_gbps"] = round(read_gbps, 1)
     roofline["stream_read_grid"] = read_grid
-    roofline["frac_of_stream_read"] = round(achieved / read_gbps, 4)
-    if traffic:
-        roofline["traffic_gbps"] = round(traffic / (phase_ms[dominant] * 1e-3) / 1e9, 1)
-
-    plain = None
-    if not args.no_plain:
-        counts_p = torch.zeros(2, dtype=torch.int64, device="cuda")
-        tune_plain = None if args.no_autotune else A.autotune(Rk, Sk, out, counts_p, flags=A.ASJ_PLAIN)
-        for _ in range(max(1, args.warmup)):
-            A.asj_join(Rk, Sk, out, counts_p, flags=A.ASJ_PLAIN)
-        ms_plain, plain_phase, _ = run_steps(A, torch, Rk, Sk, out, counts_p, args.steps, flags=A.ASJ_PLAIN)
-        assert int(counts_p[0]) == n_pairs, "plain hash join disagrees on |T|"
-        plain = {"ms_per_step": round(ms_plain, 4), "value": round(w.S.n / (ms_plain * 1e-3), 1),
-                 "unit": "probe tuples/s", "slots_compared": int(counts_p[1]),
-                 "phases_ms": {k: round(v, 4) for k, v in plain_phase.items()},
-                 "signature_join_speedup": round(ms_plain / ms_step, 3), "autotune": tune_plain}
-        log(f"plain hash join: {ms_plain:.3f} ms/step")
-        # control: the same key hash kept in the table as a 32-bit fingerprint
-        # (isolates what the algebraic signature adds over any stored fingerprint)
-        tune_fp = None if args.no_autotune else A.autotune(Rk, Sk, out, counts_p, flags=A.ASJ_FINGERPRINT)
-        for _ in range(max(1, args.warmup)):
-            A.asj_join(Rk, Sk, out, counts_p, flags=A.ASJ_FINGERPRINT)
-        ms_fp, fp_phase, _ = run_steps(A, torch, Rk, Sk, out, counts_p, args.steps, flags=A.ASJ_FINGERPRINT)
-        assert int(counts_p[0]) == n_pairs, "fingerprint hash join disagrees on |T|"
-        plain["fingerprint_control"] = {
-            "ms_per_step": round(ms_fp, 4), "value": round(w.S.n / (ms_fp * 1e-3), 1), "candidates": int(counts_p[1]),
-            "phases_ms": {k: round(v, 4) for k, v in fp_phase.items()},
-            "signature_join_speedup": round(ms_fp / ms_step, 3), "autotune": tune_fp}
-        log(f"fingerprint control: {ms_fp:.3f} ms/step")
+    roofline["frac_of_stream_read"] = round(roofline["achieved"] / read_gbps, 4)
 
     if args.calibrate_copy > 0:
         nb = int(args.calibrate_copy)
@@ -675,6 +735,14 @@ def main():
     host = None
     if args.host_budget > 0:
         host = bench_host(A, torch, w, expected, args.host_budget, Sk)
+    dna = None
+    if args.dna_scale > 0 and args.workload != "dna":
+        dna, hd = measure_single(A, torch, W, "dna", 3, args.dna_scale, max(5, args.steps // 2), args.warmup,
+                                 not args.no_autotune, plain_too=not args.no_plain, traffic_ok=traffic_ok)
+        dna["workload"] = WORKLOADS["dna"] + (f" (scale {args.dna_scale:g})" if args.dna_scale != 1 else "")
+        del hd
+        torch.cuda.empty_cache()
+        log(f"dna: {dna}")
     batched = None
     if args.batch_scale > 0:
         t = time.perf_counter()
@@ -684,6 +752,8 @@ def main():
         batched = bench_batch(A, torch, bw, max(3, args.steps // 2), args.warmup, autotune=not args.no_autotune)
         batched["workload"] = (f"batch of 256 joins at {args.batch_scale:g} scale: |R_j| log-uniform 100-200k, "
                                f"|S_j| = U(1,8)|R_j|, XML-like keys log-uniform 16-2048 B, 25% copies")
+        del bw
+        torch.cuda.empty_cache()
         log(f"batch: {batched}")
     tiny_single = bench_tiny_latency(A, torch, W) if args.tiny_instances > 0 else None
     if tiny_single:
@@ -699,8 +769,10 @@ def main():
         log(f"tiny batch: {tiny_batch}")
 
     sweep = None
-    if args.length_sweep:
-        sweep = bench_length_sweep(A, torch, W, max(3, args.steps // 4))
+    if args.sweep_lengths:
+        sweep = bench_length_sweep(A, torch, W, max(3, args.steps // 4),
+                                   lengths=[int(x) for x in args.sweep_lengths.split(",")],
+                                   autotune=not args.no_autotune)
 
     served = None
     if args.serve_scale > 0:
@@ -757,12 +829,16 @@ def main():
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "scale": args.scale, "seed": seed,
                    "R": w.R.n, "S": w.S.n, "key_bytes": w.R.nbytes + w.S.nbytes, "signature": "GF(2^16), n=2",
                    "load_factor": lf, "keys_per_window": tune["keys_per_window"] if tune else 64,
-                   "probe_schedule": tune["schedule"] if tune else "fused", "pairs": n_pairs, "candidates": n_cand, "parallelism": "1 GPU"},
-        "hbm_gbps_step": round(step_gbps, 1),
-        "frac_peak_step": round(step_gbps / HBM_PEAK_GBPS, 4),
-        "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+                   "grid_rounds": tune["grid_rounds"] if tune else 2,
+                   "probe_schedule": tune["schedule"] if tune else "fused", "pairs": n_pairs,
+                   "candidates": main_res["candidates"], "parallelism": "1 GPU"},
+        "hbm_gbps_step": main_res["hbm_gbps_step"],
+        "frac_peak_step": main_res["frac_peak_step"],
+        "phases_ms": main_res["phases_ms"],
         "roofline": roofline,
-        "plain_hash_join": plain,
+        "plain_hash_join": main_res.get("plain_hash_join"),
+        "fingerprint_control": main_res.get("fingerprint_control"),
+        "dna_join": dna,
         "batched": batched,
         "tiny_batched": tiny_batch,
         "tiny_single_join_latency": tiny_single,
@@ -772,7 +848,7 @@ def main():
         "autotune": tune,
         "length_sweep": sweep,
         "cpu_baseline": cpu,
-        "check": {"pairs_match_expected": n_pairs == expected and check == n_pairs},
+        "check": {"pairs_match_expected": main_res["pairs_match_expected"]},
     }
     print(json.dumps(line), flush=True)
 
