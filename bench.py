@@ -66,8 +66,9 @@ def parse():
                     help="size of the 256-join batch workload run beside the main line (0 = skip)")
     ap.add_argument("--dna-scale", type=float, default=1.0,
                     help="size of the DNA join run beside the main line (0 = skip)")
-    ap.add_argument("--tiny-instances", type=int, default=128,
-                    help="independent tiny joins run as one batch beside the main line (0 = skip)")
+    ap.add_argument("--tiny-instances", type=int, default=256,
+                    help="independent tiny joins run as one batch beside the main line (0 = skip); the stream of "
+                         "batches alternates between two such sets of distinct instances")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="size of the resident build side of the serving run (1.0 = 10M keys; 0 = skip)")
     ap.add_argument("--serve-arrivals", type=int, default=400)

@@ -12,7 +12,7 @@ times.
 * asj_join_batch over all 256 joins of the batched workload (~14 GB): every
   join compared pair for pair with the oracle's hash join (the oracle calls
   run in a thread pool; they release the GIL).
-* 128 independent tiny joins (655 MB) in one batch.
+* 256 independent tiny joins (1.3 GB) in one batch.
 * The continuous-batching server over the resident 10M-key build side with
   requests of up to 1M keys, and the partitioned host-memory join.
 
@@ -225,12 +225,13 @@ def test_full_size_host_join_partitioned_equals_oracle(A, oracle, wl):
 
 
 def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
-    """128 independent tiny joins (R = S = 10k keys of 256 B each, 655 MB) in
+    """256 independent tiny joins (R = S = 10k keys of 256 B each, 1.3 GB) in
     one batch, the benchmark's throughput configuration (every join's table
     built in LDS; options left to the library): every join has exactly the
     generator's 2000 matches and equals the oracle pair for pair, candidate
     counts included."""
-    parts = [wl.tiny(seed=1 + i) for i in range(128)]
+    J = 256
+    parts = [wl.tiny(seed=1 + i) for i in range(J)]
     def cat(rels):
         lens = np.concatenate([r.lengths() for r in rels])
         data = np.concatenate([r.data[:r.offsets[-1]] for r in rels] + [np.zeros(16, np.uint8)])
@@ -240,10 +241,10 @@ def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
     Rf, Sf = cat([p.R for p in parts]), cat([p.S for p in parts])
     r_seg = np.concatenate([[0], np.cumsum([p.R.n for p in parts])]).astype(np.int64)
     s_seg = np.concatenate([[0], np.cumsum([p.S.n for p in parts])]).astype(np.int64)
-    b = wl.BatchWorkload("tiny x128", Rf, Sf, r_seg, s_seg)
-    note(f"tiny instances: joins=128 R={Rf.n} S={Sf.n} bytes={Rf.nbytes + Sf.nbytes}")
+    b = wl.BatchWorkload(f"tiny x{J}", Rf, Sf, r_seg, s_seg)
+    note(f"tiny instances: joins={J} R={Rf.n} S={Sf.n} bytes={Rf.nbytes + Sf.nbytes}")
     R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
     out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg)
     assert (counts == 2000).all()
-    check_batch_output(oracle, b, oracle_batch(oracle, b), out.cpu().numpy(), oseg, counts, cands, "tiny x128")
-    note("tiny instances: all 128 joins (2000 pairs each) equal the oracle")
+    check_batch_output(oracle, b, oracle_batch(oracle, b), out.cpu().numpy(), oseg, counts, cands, b.name)
+    note(f"tiny instances: all {J} joins (2000 pairs each) equal the oracle")
