@@ -192,19 +192,6 @@ hipError_t launch_sign_for(const asj_keys *k, asj_sig_params sig, int plain, uin
 
 bool sig64(asj_sig_params s) { return s.f == 16 && s.nsym == 4; }
 
-// Keys per window for signing n keys on their own (the build side, or
-// asj_signature): 64, halved while that leaves fewer than 2048 windows,
-// down to 16, unless n is small enough for an LDS table (a latency-bound
-// join, whose few blocks load the GF tables only once each).  Few keys are
-// usually long ones: 32k keys of 4 KB in windows of 64 kept one eighth of
-// the compute units busy.
-int sign_kpw_for(int64_t n)
-{
-    int kpw = ASJ_WAVE;
-    while (kpw > 16 && n > ASJ_LOCAL_ROWS && n / kpw < 2048) kpw >>= 1;
-    return kpw;
-}
-
 template <typename T>
 hipError_t alloc_async(T **p, size_t count, hipStream_t st)
 {
@@ -288,7 +275,7 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin(plain ? "hash_build" : fp ? "fp_build" : "sign_build", st);
         le = launch_sign_for(r, sig, plain || fp, sig_r, g_dev[dev].tab, st, t->status, t->sig_hi, 1, nullptr,
-                             sign_kpw_for(r->n));
+                             0 /* windows sized by the kernel */);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
@@ -593,7 +580,7 @@ int join_local_single(const asj_keys *r, const asj_keys *s, const asj_opts *opts
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, nullptr, sign_kpw_for(r->n));
+        e = launch_sign_for(r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, nullptr, 0);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         asj_probe_args a = {};
@@ -660,7 +647,7 @@ int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hip
     int dev = 0;
     rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
-    const int kpw = sign_kpw_for(keys->n);
+    const int kpw = 0; // windows sized by the kernel from the keys' mean length
     if (sig64(sig)) // little-endian 64-bit signatures: the low word, then the high word
         TIMED("signature",
               launch_sign_for(keys, sig, 0, sig_out, g_dev[dev].tab, st, nullptr, sig_out + 1, 2, nullptr, kpw));
@@ -868,8 +855,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
                                win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap,
                                (uint32_t *)rmatch, rmatch ? (b->r.n + 3) / 4 : 0};
         tim_begin(plain ? "hash_build" : "sign_build", st);
-        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep,
-                            sign_kpw_for(b->r.n));
+        e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep, 0);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         tim_begin("insert", st);

@@ -302,7 +302,8 @@ hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
 // receives the high word (components 3, 4).
 // prep (may be NULL): the batch's slot fill and window maps, written by the
 // kernel's blocks before they sign (one launch fewer per batch).
-// kpw: keys per signing window (1 .. 64; fewer for long keys, see sign.hip).
+// kpw: keys per signing window (1 .. 64), or 0 for asj_auto_kpw's choice
+// from the keys' mean length, made by the kernel.
 struct asj_batch_prep;
 hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out, const uint16_t *tab,
                            int grid_cap, hipStream_t st, const int32_t *status = nullptr,
@@ -352,6 +353,37 @@ struct asj_join_desc {
 // (bucketed by mix32, entries sorted by bucket), instead of a segment of the
 // device-memory slot array.
 #define ASJ_LOCAL_ROWS 10240
+
+// Blocks of `kernel` that the device holds at once (blocks per compute unit
+// from the occupancy calculator x compute units); 0 when the runtime cannot
+// say.
+inline int64_t asj_resident_blocks(const void *kernel, int block)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || cus <= 0 || per <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (int64_t)cus * per;
+}
+
+// Keys per signing window when the caller leaves the choice to the keys
+// (kpw = 0): the power of two in 4 .. 64 nearest (on a log scale) to
+// 32768 / mean key length, i.e. windows of about eight passes of 64 chunks
+// of 64 bytes.  Measured on the signature kernel alone, this choice came
+// within 11% of the best window size (and within 4% on average) over seven
+// sets from 32k keys of 4 KB to 1M keys of 16 bytes to 1M DNA keys of
+// 5.5 KB; windows of 64 throughout were up to 47% slower (few long keys
+// leave most compute units idle, and long windows balance poorly).
+// bytes / n is the mean key length; 46341 = 32768 * sqrt(2).
+__host__ __device__ inline int asj_auto_kpw(int64_t n, int64_t bytes)
+{
+    int kpw = ASJ_WAVE;
+    while (kpw > 4 && 46341 * n < (int64_t)kpw * bytes) kpw >>= 1;
+    return kpw;
+}
 
 // A batch's preparation after its plan: empty slots up to the planned total,
 // then the window maps (block b writes the windows of joins b, b + nblocks,

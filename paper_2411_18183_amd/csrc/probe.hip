@@ -637,21 +637,6 @@ __global__ __launch_bounds__(256) void unmatched_build_kernel(const uint8_t *__r
     }
 }
 
-// Blocks of `kernel` that the device holds at once (blocks per compute unit
-// from the occupancy calculator x compute units); 0 when the runtime cannot
-// say.
-int64_t resident_blocks(const void *kernel, int block)
-{
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || cus <= 0 || per <= 0) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return (int64_t)cus * per;
-}
-
 template <int MODE, int NSYM, int PLAIN, int VERIFY, int PRESIGNED>
 hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hipStream_t st)
 {
@@ -661,9 +646,9 @@ hipError_t launch(const asj_probe_args *a, const uint16_t *tab, int grid_cap, hi
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
     if (a->grid_rounds > 0) { // the grid in rounds of resident blocks
-        static const int64_t res_batch = resident_blocks(
+        static const int64_t res_batch = asj_resident_blocks(
             reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, PRESIGNED, 0>), kBlock);
-        static const int64_t res_single = resident_blocks(
+        static const int64_t res_single = asj_resident_blocks(
             reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, PRESIGNED, 0>), kBlock);
         const int64_t resident = a->njoins > 0 ? res_batch : res_single;
         if (resident > 0 && blocks > resident * a->grid_rounds) blocks = resident * a->grid_rounds;
@@ -686,7 +671,7 @@ hipError_t launch_local(const asj_probe_args *a, const uint16_t *tab, hipStream_
 {
     constexpr int kBlock = Shape<0, 1>::block;
     static const int64_t resident =
-        resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, 0, 1>), kBlock);
+        asj_resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 1, 0, 1>), kBlock);
     if (resident <= 0) return hipErrorInvalidValue; // the kernel does not fit a compute unit
     int64_t blocks = resident * (a->grid_rounds > 0 ? a->grid_rounds : 1);
     const int64_t most = (a->nwin_cap + a->nwin_l_cap) / Shape<0, 1>::waves + 2;
@@ -752,7 +737,7 @@ hipError_t launch_local_single(const asj_probe_args *a, const uint16_t *tab, hip
     constexpr int kBlock = Shape<0, 1>::block;
     constexpr int kWaves = Shape<0, 1>::waves;
     static const int64_t resident =
-        resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, 0, 1>), kBlock);
+        asj_resident_blocks(reinterpret_cast<const void *>(&probe_kernel<MODE, NSYM, PLAIN, VERIFY, 0, 0, 1>), kBlock);
     if (resident <= 0) return hipErrorInvalidValue;
     const int64_t nwin = (a->n + a->keys_per_window - 1) / a->keys_per_window;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;

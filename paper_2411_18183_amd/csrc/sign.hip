@@ -9,13 +9,21 @@ namespace {
 // many waves, so two blocks (32 waves) fit a CU instead of three blocks of 8.
 constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / ASJ_WAVE;
+// Grid, when the kernel sizes the windows: this many rounds of the blocks
+// the device holds at once, each block looping over windows.  Measured on
+// 32k to 1.3M keys of 64 B to 5.5 KB: one round balanced long keys poorly
+// (DNA keys 10% slower), eight rounds cost short keys the most block
+// starts; four came within 4% of the best of 1, 2, 4 and 8 on every set
+// but 1M keys of 64 bytes (15%, 2.5 us).
+constexpr int kSignRounds = 4;
 
 // out[k * stride] = signature of key k (its low word with four GF(2^16)
 // components, whose high word goes to out_hi[k * stride]).  With has_prep
 // the blocks first do their part of a batch's preparation.  A wave signs
-// windows of kpw consecutive keys (1 .. 64): long keys fill a window's
-// passes with few keys, and fewer keys per window give few long keys
-// enough windows to occupy every compute unit.
+// windows of kpw consecutive keys (1 .. 64, or 0: chosen here from the
+// keys' mean length by asj_auto_kpw): long keys fill a window's passes with
+// few keys, and fewer keys per window give few long keys enough windows to
+// occupy every compute unit.
 template <int MODE, int NSYM>
 __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict__ data,
                                                       const int64_t *__restrict__ off, int64_t n,
@@ -27,6 +35,13 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
     if (has_prep) asj_batch_prep_run(prep, blockIdx.x, gridDim.x, threadIdx.x, kBlock);
     if (status && *status != 0) return; // the inputs failed validation: read no key (same for every thread)
+    const int64_t end = off[n]; // the keys' bytes end here
+    if (kpw <= 0) {
+        // the grid was sized for the smallest windows; blocks beyond the
+        // chosen windows leave before they load the GF tables
+        kpw = asj_auto_kpw(n, end - off[0]);
+        if ((int64_t)blockIdx.x * kWaves * kpw >= n) return; // block-uniform
+    }
     __shared__ uint16_t tab[asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
     __shared__ int32_t kex[kWaves][ASJ_WAVE];
@@ -38,7 +53,6 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
     const int64_t nwin = (n + kpw - 1) / kpw;
-    const int64_t end = off[n]; // the keys' bytes end here
     for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
         const int64_t k = w * kpw + lane;
         const bool mine = lane < kpw && k < n;
@@ -63,9 +77,19 @@ hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride
                   const int32_t *status, const asj_batch_prep *prep, int kpw, hipStream_t st)
 {
     const asj_batch_prep none = {};
-    const int64_t nwin = (k->n + kpw - 1) / kpw;
+    // sets small enough for an LDS-table join keep windows of 64 (latency-
+    // bound: each of their few blocks loads the GF tables once, and no
+    // block waits for the key bytes' extent before it does)
+    if (kpw <= 0 && k->n <= ASJ_LOCAL_ROWS) kpw = ASJ_WAVE;
+    const int kmin = kpw > 0 ? kpw : 4; // 0: the kernel picks 4 .. 64
+    const int64_t nwin = (k->n + kmin - 1) / kmin;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
+    if (kpw <= 0) {
+        static const int64_t resident =
+            asj_resident_blocks(reinterpret_cast<const void *>(&sign_kernel<MODE, NSYM>), kBlock);
+        if (resident > 0 && blocks > resident * kSignRounds) blocks = resident * kSignRounds;
+    }
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((sign_kernel<MODE, NSYM>), dim3((unsigned)blocks), dim3(kBlock), 0, st, k->data, k->offsets,
                        k->n, out, out_hi, stride, tab, status, prep ? *prep : none, prep ? 1 : 0, kpw);
@@ -80,7 +104,7 @@ hipError_t asj_launch_sign(int mode, int nsym, const asj_keys *k, uint32_t *out,
 {
     if (k->n == 0) return prep ? asj_launch_batch_prep(prep, st) : hipSuccess;
     if (stride < 1) return hipErrorInvalidValue;
-    if (kpw < 1 || kpw > ASJ_WAVE) kpw = ASJ_WAVE;
+    if (kpw < 0 || kpw > ASJ_WAVE) kpw = ASJ_WAVE; // 0: chosen by the kernel
     if (mode == ASJ_MODE_SIG16 && nsym == 4) {
         if (!out_hi) return hipErrorInvalidValue;
         return launch<ASJ_MODE_SIG16, 4>(k, out, out_hi, stride, tab, grid_cap, status, prep, kpw, st);
