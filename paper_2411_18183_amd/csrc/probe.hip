@@ -282,6 +282,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
     asj_pair *wout = kout[wave];
     int nstage = 0;     // staged pairs (wave-uniform)
     int stage_join = 0; // join of the current window (batch mode)
+    int64_t join_cand = 0; // candidates of stage_join not yet added to its count (batch mode)
     // reserve output space for the staged pairs with one atomic and copy them out
     // (every lambda below is inlined at each use: a call would spill the
     // kernel's registers)
@@ -306,6 +307,15 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         }
         asj_wave_sync();
         nstage = 0;
+    };
+    // batch mode: the staged pairs and the candidate count of stage_join out
+    // before the wave's windows move to another join
+    auto flush_join = [&]() __attribute__((always_inline)) {
+        flush();
+        if (BATCH && join_cand) {
+            if (lane == 0) atomicAdd((unsigned long long *)(a.cand_count + stage_join), (unsigned long long)join_cand);
+            join_cand = 0;
+        }
     };
 
     // the matching pairs themselves (every kind but the semi- and anti-join)
@@ -497,20 +507,19 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
             if (nstage > kStage - ASJ_WAVE) flush();
         }
         if (BATCH) {
-            // a join's pairs are all out before its rows are counted done;
-            // an LDS-table block stays on one join until its share of the
-            // join's windows is done, so it flushes per window only for the
-            // completion clocks
-            if (!(LOCAL && lw) || a.done_clock) flush();
-            const int cands = wave_sum(lane_cand);
-            const unsigned long long nrows = __popcll(__ballot(valid));
-            if (lane == 0 && nrows) {
-                if (a.cand_count && cands) atomicAdd((unsigned long long *)(a.cand_count + j), (unsigned long long)cands);
-                if (a.done_clock) { // the wave that finishes a join's last rows stamps its completion
+            // staged pairs and the candidate count stay with the wave until
+            // its windows move to another join (or the stage fills); only
+            // the completion clocks need a join's pairs out after every
+            // window, before its rows are counted done
+            if (a.done_clock) {
+                flush();
+                const unsigned long long nrows = __popcll(__ballot(valid));
+                if (lane == 0 && nrows) { // the wave that finishes a join's last rows stamps its completion
                     const unsigned long long before = atomicAdd((unsigned long long *)(a.rows_done + j), nrows);
                     if ((int64_t)(before + nrows) == a.s_seg[j + 1] - a.s_seg[j]) a.done_clock[j] = wall_clock64();
                 }
             }
+            if (a.cand_count) join_cand += (uint32_t)__builtin_amdgcn_readfirstlane(wave_sum(lane_cand));
         }
     };
 
@@ -535,7 +544,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 const int64_t nxt = win + kWaves < w_end ? k0 + (int64_t)kWaves * kpw : -1;
                 window(j, k0, (int)min((int64_t)kpw, s1 - k0), nullptr, 0, r0, nxt, true);
             }
-            flush(); // the next join's pairs go to another output segment
+            flush_join(); // the next join's pairs go to another output segment
             w = w_end;
         }
     }
@@ -565,6 +574,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 const asj_join_desc d = a.desc[j];
                 slots = a.slots + d.tbase;
                 mask = d.mask;
+                if (j != stage_join) flush_join();
                 stage_join = j;
             }
             if constexpr (kLocalSingle)
@@ -573,7 +583,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
                 window(j, k0, rows, slots, mask, 0, win + stride, false);
         }
     }
-    flush();
+    flush_join();
     if (!BATCH && a.cand_count && lane == 0 && wave_cand)
         atomicAdd((unsigned long long *)a.cand_count, (unsigned long long)wave_cand);
 }

@@ -95,6 +95,26 @@ def test_signature_many_windows_and_ragged_tail(A, oracle, wl):
     assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
 
 
+# Above 10240 keys the signature kernel sizes its windows from the keys'
+# mean length (4 .. 64 keys, about eight passes of 64 chunks each): mean
+# lengths chosen so that each window size is taken, with short keys and
+# empty keys mixed in, a ragged last window and an unaligned arena.
+@pytest.mark.parametrize("mean,params", [(400, (16, 2)), (1000, (16, 2)), (2000, (16, 4)), (4000, (16, 2)),
+                                         (8000, (16, 2)), (2000, (8, 4)), (700, (16, 1))])
+def test_signature_every_window_size(A, oracle, wl, mean, params):
+    rng = np.random.default_rng(mean + params[1])
+    n = 10240 + 1 + int(rng.integers(0, 300))
+    lens = rng.integers(mean // 2, mean + mean // 2 + 1, size=n)
+    short = rng.uniform(size=n) < 0.05
+    lens[short] = rng.integers(0, 70, size=int(short.sum()))
+    data = rng.integers(0, 256, size=int(lens.sum()) + 16, dtype=np.uint8)
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    rel = wl.unaligned_copy(wl.Relation(data, off, np.arange(n, dtype=np.int32)), int(mean) % 7)
+    f, nsym = params
+    assert np.array_equal(gpu_sigs(A, rel, f, nsym), oracle.signatures(rel, f, nsym))
+
+
 @pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("seed", range(10))
 def test_join_small_random(A, oracle, wl, seed, sched):
