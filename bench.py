@@ -169,25 +169,28 @@ def tiny_instances(W, count: int, seed0: int = 1):
     return W.BatchWorkload(f"tiny x{count}", R, S, r_seg, s_seg, {"seed0": seed0})
 
 
-def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autotune: bool = True):
-    """Batched launch sequence vs one asj_join per join, on the same inputs."""
+def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autotune: bool = True, flags: int = 0):
+    """Batched launch sequence vs one asj_join per join, on the same inputs
+    (flags: extra batch flags, e.g. ASJ_LOCAL_ONLY when every join is small)."""
     import numpy as np
     J = bw.njoins
     R = A.DeviceKeys.from_host(bw.R)
     S = A.DeviceKeys.from_host(bw.S)
-    out, oseg, counts, cands, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg)
+    out, oseg, counts, cands, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg, flags=flags)
     dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
     r_seg, s_seg, out_seg = dev(bw.r_seg), dev(bw.s_seg), dev(oseg)
     tune = None
     if autotune:  # setup, not timed; the timed calls leave the options to the library
-        tune = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"))
+        tune = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"),
+                                flags=flags)
     cnt = torch.zeros(J, dtype=torch.int64, device="cuda")
     clock = torch.zeros(J + 1, dtype=torch.int64, device="cuda")
     ws = torch.empty(A.asj_batch_workspace_bytes(J, bw.R.n, bw.S.n), dtype=torch.uint8, device="cuda")
     # throughput without completion stamps (they cost an atomic per window);
     # the per-join latencies come from separate runs that ask for them
-    run = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, None, workspace=ws)
-    run_clock = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, clock, workspace=ws)
+    run = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, None, workspace=ws, flags=flags)
+    run_clock = lambda: A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnt, None, clock, workspace=ws,
+                                         flags=flags)
     for _ in range(max(1, warmup)):
         run()
     torch.cuda.synchronize()
@@ -206,7 +209,7 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     lat = np.concatenate(lat)
     assert (cnt.cpu().numpy() == counts).all(), "batched counts changed between runs"
     # the plain byte-compare hash join through the same batched path
-    flags_p = A.ASJ_PLAIN
+    flags_p = A.ASJ_PLAIN | flags
     tune_plain = None
     if autotune:
         tune_plain = A.autotune_batch(R, S, r_seg, s_seg, out, out_seg, torch.zeros(J, dtype=torch.int64, device="cuda"),
@@ -286,7 +289,7 @@ def bench_batch(A, torch, bw, steps: int, warmup: int, graph: bool = True, autot
     }
 
 
-def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 4):
+def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 4, flags: int = 0):
     """A stream of batches over distinct instances: the batch workloads in
     `bws` (each many tiny joins) alternate, one batch per call, first on one
     stream, then round-robin over `nlanes` streams with a workspace and
@@ -298,7 +301,7 @@ def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 4):
     ins = []
     for bw in bws:
         R, S = A.DeviceKeys.from_host(bw.R), A.DeviceKeys.from_host(bw.S)
-        out, oseg, counts, _, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg)
+        out, oseg, counts, _, _ = A.join_batch(R, S, bw.r_seg, bw.s_seg, flags=flags)
         ins.append((R, S, dev(bw.r_seg), dev(bw.s_seg), dev(oseg), out.shape[0], counts, bw))
     J = bws[0].njoins
     assert all(b.njoins == J for b in bws)
@@ -314,7 +317,7 @@ def bench_batch_stream(A, torch, bws, batches: int = 200, nlanes: int = 4):
         R, S, r_seg, s_seg, out_seg, _, _, _ = ins[k % len(ins)]
         ws, out, cnts, _ = lanes[lane]
         A.asj_join_batch(R, S, r_seg, s_seg, out, out_seg, cnts[k % len(ins)], None, None, workspace=ws,
-                         stream=stream)
+                         stream=stream, flags=flags)
     def timed(multi):
         ran = set()
         for k in range(8):  # warm-up, every lane and input
@@ -762,10 +765,14 @@ def main():
     tiny_batch = None
     if args.tiny_instances > 0:
         tw = tiny_instances(W, args.tiny_instances)
-        tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup, autotune=not args.no_autotune)
+        # every tiny join has 10k build rows: LDS tables only, stated to the library
+        tiny_batch = bench_batch(A, torch, tw, max(5, args.steps), args.warmup, autotune=not args.no_autotune,
+                                 flags=A.ASJ_LOCAL_ONLY)
         tiny_batch["workload"] = f"{args.tiny_instances} independent tiny joins (R=S=10k x 256 B) in one batch"
         tw2 = tiny_instances(W, args.tiny_instances, seed0=args.tiny_instances + 1)
-        tiny_batch["stream_of_batches"] = bench_batch_stream(A, torch, [tw, tw2], batches=max(200, 10 * args.steps))
+        tiny_batch["stream_of_batches"] = bench_batch_stream(A, torch, [tw, tw2], batches=max(200, 10 * args.steps),
+                                                             flags=A.ASJ_LOCAL_ONLY)
+        tiny_batch["flags"] = "ASJ_LOCAL_ONLY"
         del tw2
         log(f"tiny batch: {tiny_batch}")
 

@@ -111,6 +111,15 @@ extern "C" {
                                 (same candidates, same output set).  The split schedule, the
                                 fingerprint control, 64-bit signatures and asj_build always
                                 use device-memory tables. */
+#define ASJ_LOCAL_ONLY 0x1000u /* asj_join_batch (and asj_autotune_batch): the caller states that
+                                every join has at most 10240 build rows, so every join is probed
+                                against an LDS table and the device-memory table build (two
+                                launches that would find nothing to insert) is skipped.  Checked
+                                on the device: a join above the limit fails the call as invalid
+                                segments do (every count -1, no key read).  With
+                                ASJ_GLOBAL_TABLES or ASJ_PROBE_SPLIT: ASJ_EINVAL (an automatic
+                                schedule resolves to the fused one).  Other entry points ignore
+                                it. */
 
 /* A relation's join attributes: key k is data[offsets[k] .. offsets[k+1]).
  * offsets must be non-decreasing (k = 0..n).  The library reads only

@@ -37,6 +37,7 @@ ASJ_LEFT_OUTER = 0x100
 ASJ_RIGHT_OUTER = 0x800
 ASJ_FINGERPRINT = 0x200
 ASJ_GLOBAL_TABLES = 0x400
+ASJ_LOCAL_ONLY = 0x1000
 
 
 class AsjError(RuntimeError):

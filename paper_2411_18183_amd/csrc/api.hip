@@ -451,7 +451,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
 
 int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, asj_sig_params *sig, float *lf,
                int *kpw, int *split, int *validate = nullptr, int *kind = nullptr, int *rounds_out = nullptr,
-               int *local_out = nullptr)
+               int *local_out = nullptr, int *local_only_out = nullptr)
 {
     int rounds_local = 2;
     int *rounds = rounds_out ? rounds_out : &rounds_local;
@@ -463,6 +463,9 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
     if (o.flags & (ASJ_SORTED | ASJ_FINGERPRINT)) return ASJ_EUNSUPPORTED;
     if (validate) *validate = (o.flags & ASJ_VALIDATE) != 0;
     if (local_out) *local_out = (o.flags & ASJ_GLOBAL_TABLES) == 0;
+    const int local_only = (o.flags & ASJ_LOCAL_ONLY) != 0;
+    if (local_only && (o.flags & (ASJ_GLOBAL_TABLES | ASJ_PROBE_SPLIT))) return ASJ_EINVAL;
+    if (local_only_out) *local_only_out = local_only;
     const int k = join_kind(o.flags);
     if (k < 0) return ASJ_EINVAL;
     if (kind) *kind = k;
@@ -472,7 +475,9 @@ int batch_opts(const asj_opts *opts, int64_t n_build, int *plain, int *verify, a
         if (rc != ASJ_OK) return rc;
         if (sig64(*sig)) return ASJ_EUNSUPPORTED; // 64-bit signatures: single joins only
     }
-    return resolve_auto(1, n_build, o, lf, kpw, split, rounds);
+    const int rc = resolve_auto(1, n_build, o, lf, kpw, split, rounds);
+    if (local_only) *split = 0; // LDS tables need the fused schedule (an explicit split was refused above)
+    return rc;
 }
 
 } // namespace
@@ -808,9 +813,10 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     int plain, verify, kpw, split;
     asj_sig_params sig;
     float lf;
-    int validate, kind, local;
+    int validate, kind, local, local_only;
     int rounds = 2;
-    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind, &rounds, &local);
+    int rc = batch_opts(opts, b->r.n, &plain, &verify, &sig, &lf, &kpw, &split, &validate, &kind, &rounds, &local,
+                        &local_only);
     if (rc != ASJ_OK) return rc;
     if (split) local = 0; // the split schedule signs the probe keys first: device-memory tables only
     BatchLayout L;
@@ -842,8 +848,8 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         hipError_t e;
         tim_begin("batch_plan", st);
         e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw,
-                                  local ? ASJ_LOCAL_ROWS : -1, desc, rows_done, b->out_count, b->cand_count,
-                                  b->done_clock, tot, status, st);
+                                  local ? ASJ_LOCAL_ROWS : -1, local_only, desc, rows_done, b->out_count,
+                                  b->cand_count, b->done_clock, tot, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
@@ -858,10 +864,12 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
         e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep, 0);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
-        tim_begin("insert", st);
-        e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, desc, win_r, tot, L.win_r_cap, slots, status, st);
-        tim_end(st);
-        if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        if (!local_only) { // otherwise no join has a device-memory table
+            tim_begin("insert", st);
+            e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, desc, win_r, tot, L.win_r_cap, slots, status, st);
+            tim_end(st);
+            if (e != hipSuccess) { out_rc = hip_fail(e); break; }
+        }
         asj_probe_args a = {};
         a.rdata = b->r.data;
         a.roff = b->r.offsets;

@@ -522,7 +522,7 @@ hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int gr
 // windows; win_r / win_s map windows to joins.
 hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
                                  int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
-                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
+                                 int local_only, asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
                                  uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st);
 hipError_t asj_launch_batch_prep(const asj_batch_prep *p, hipStream_t st);
 hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,

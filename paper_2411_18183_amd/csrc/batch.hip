@@ -20,12 +20,13 @@ constexpr int kPlanBlock = 1024;
 // LDS-table probe windows) and their prefix sums, counters zeroed, batch
 // start clock.  Segment arrays that do not cover the
 // relations exactly (first bound 0, last bound the row count, no bound
-// decreasing), or segments that would not fit slot_cap slots, set *status
-// to ASJ_EINVAL so that no later kernel of the batch touches the slots.
+// decreasing), segments that would not fit slot_cap slots, or (local_only)
+// a join too large for an LDS table, set *status to ASJ_EINVAL so that no
+// later kernel of the batch touches the slots or reads a key.
 __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *__restrict__ r_seg,
                                                                 const int64_t *__restrict__ s_seg, int32_t J,
                                                                 int64_t n_r, int64_t n_s, int64_t slot_cap, float lf,
-                                                                int kpw, int64_t local_rows,
+                                                                int kpw, int64_t local_rows, int local_only,
                                                                 asj_join_desc *__restrict__ desc,
                                                                 int64_t *__restrict__ rows_done,
                                                                 int64_t *__restrict__ out_count,
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
             if (nr <= local_rows) { // no segment, no build windows: an LDS table
                 v[3] = nw;
             } else {
+                if (local_only) bad = 1; // the caller promised LDS tables only; nothing builds device tables
                 uint64_t cap = 64;
                 while ((double)cap * lf < (double)nr) cap <<= 1;
                 v[0] = cap;
@@ -171,13 +173,13 @@ int grid_for(int64_t n, int block, int cap)
 
 hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
                                  int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
-                                 asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
+                                 int local_only, asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
                                  uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st)
 {
     if (keys_per_window < 1 || keys_per_window > ASJ_WAVE) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s, slot_cap,
-                       load_factor, keys_per_window, local_rows, desc, rows_done, out_count, cand_count, done_clock,
-                       tot, status);
+                       load_factor, keys_per_window, local_rows, local_only, desc, rows_done, out_count, cand_count,
+                       done_clock, tot, status);
     return hipGetLastError();
 }
 

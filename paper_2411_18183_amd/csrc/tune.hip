@@ -97,6 +97,7 @@ std::vector<asj_opts> grid(const asj_opts &base, int64_t n_build, bool batch)
             for (uint32_t sched : {ASJ_PROBE_FUSED, ASJ_PROBE_SPLIT})
                 for (int rounds : kGridRounds) {
                     if (sched == ASJ_PROBE_SPLIT && base.sig.f == 16 && base.sig.nsym == 4) continue; // fused only
+                    if (sched == ASJ_PROBE_SPLIT && (base.flags & ASJ_LOCAL_ONLY)) continue;         // LDS tables: fused
                     asj_opts o = base;
                     o.load_factor = lf;
                     o.keys_per_window = kpw;

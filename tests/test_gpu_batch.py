@@ -209,6 +209,38 @@ def test_batch_invalid_segments_report_minus_one(A, wl, case):
     assert counts.tolist() == [1, 1, 1]
 
 
+@pytest.mark.parametrize("kind", ["inner", "left", "full"])
+def test_batch_local_only_flag(A, oracle, wl, kind):
+    """ASJ_LOCAL_ONLY skips the device-memory table build: a batch whose
+    joins all have at most 10240 build rows gives the oracle's output with
+    it; one join above the limit fails the whole call on the device (every
+    count -1), and the flag is refused beside the split schedule or
+    device-memory tables."""
+    sizes = [(1, 300, 24), (700, 5000, 70), (10240, 12000, 130), (0, 50, 8), (64, 0, 200), (5000, 5000, 9)]
+    parts = [wl.fixed_length(seed=70 + i, m=m, n=n, key_len=L, copy_frac=0.3 if m else 0.0)
+             for i, (m, n, L) in enumerate(sizes)]
+    Rf, Sf, r_seg, s_seg = concat(wl, parts)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    flags = KINDS[kind] | A.ASJ_LOCAL_ONLY
+    caps = np.diff(s_seg) + np.diff(r_seg) + 16
+    got, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags)
+    goth = got.cpu().numpy()
+    for k, w in enumerate(parts):
+        want = oracle.join_variant(w.R, w.S, kind) if kind != "inner" else oracle.join_signature(w.R, w.S)[0]
+        assert counts[k] == len(want), (kind, k)
+        assert np.array_equal(oracle.sort_pairs(goth[oseg[k]:oseg[k] + counts[k]]), want), (kind, k)
+    if kind == "inner":
+        assert all(cands[k] == oracle.join_signature(w.R, w.S)[1] for k, w in enumerate(parts))
+    big = parts + [wl.fixed_length(seed=90, m=10241, n=2000, key_len=40, copy_frac=0.3)]
+    Rb, Sb, rb_seg, sb_seg = concat(wl, big)
+    _, _, bcounts, _, _ = A.join_batch(A.DeviceKeys.from_host(Rb), A.DeviceKeys.from_host(Sb), rb_seg, sb_seg,
+                                        flags=flags)
+    assert (bcounts == -1).all()
+    for extra in (A.ASJ_GLOBAL_TABLES, A.ASJ_PROBE_SPLIT):
+        with pytest.raises(A.AsjError):
+            A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags | extra)
+
+
 @pytest.mark.parametrize("sig", [(16, 1), (8, 2), (8, 4)])
 @pytest.mark.parametrize("verify", [True, False])
 def test_batch_lds_tables_other_signatures(A, oracle, wl, sig, verify):
