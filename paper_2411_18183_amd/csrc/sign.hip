@@ -12,10 +12,12 @@ constexpr int kWaves = kBlock / ASJ_WAVE;
 // Grid, when the kernel sizes the windows: this many rounds of the blocks
 // the device holds at once, each block looping over windows.  Measured on
 // 32k to 1.3M keys of 64 B to 5.5 KB: one round balanced long keys poorly
-// (DNA keys 10% slower), eight rounds cost short keys the most block
-// starts; four came within 4% of the best of 1, 2, 4 and 8 on every set
-// but 1M keys of 64 bytes (15%, 2.5 us).
-constexpr int kSignRounds = 4;
+// (DNA keys 10% slower); four and eight rounds came within 2% of each
+// other on every set but 1M keys of 64 bytes (eight: 7%, 1.5 us slower)
+// and 1M DNA keys (eight: 2% faster), and the batch whose blocks also
+// write the slot fill and window maps (256 joins, 6.3M build keys) signed
+// 6% slower on four rounds than on eight.
+constexpr int kSignRounds = 8;
 
 // out[k * stride] = signature of key k (its low word with four GF(2^16)
 // components, whose high word goes to out_hi[k * stride]).  With has_prep
