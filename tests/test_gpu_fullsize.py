@@ -227,7 +227,8 @@ def test_full_size_host_join_partitioned_equals_oracle(A, oracle, wl):
 def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
     """256 independent tiny joins (R = S = 10k keys of 256 B each, 1.3 GB) in
     one batch, the benchmark's throughput configuration (every join's table
-    built in LDS; options left to the library): every join has exactly the
+    built in LDS, stated with ASJ_LOCAL_ONLY; options left to the library):
+    every join has exactly the
     generator's 2000 matches and equals the oracle pair for pair, candidate
     counts included."""
     J = 256
@@ -244,7 +245,10 @@ def test_full_size_tiny_instances_batch_equals_oracle(A, oracle, wl):
     b = wl.BatchWorkload(f"tiny x{J}", Rf, Sf, r_seg, s_seg)
     note(f"tiny instances: joins={J} R={Rf.n} S={Sf.n} bytes={Rf.nbytes + Sf.nbytes}")
     R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
-    out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg)
-    assert (counts == 2000).all()
-    check_batch_output(oracle, b, oracle_batch(oracle, b), out.cpu().numpy(), oseg, counts, cands, b.name)
-    note(f"tiny instances: all {J} joins (2000 pairs each) equal the oracle")
+    want = oracle_batch(oracle, b)
+    # as timed: the batch states that every join has an LDS table; and without the statement
+    for flags in (A.ASJ_LOCAL_ONLY, 0):
+        out, oseg, counts, cands, _ = A.join_batch(R, S, r_seg, s_seg, flags=flags)
+        assert (counts == 2000).all()
+        check_batch_output(oracle, b, want, out.cpu().numpy(), oseg, counts, cands, f"{b.name} flags={flags:#x}")
+    note(f"tiny instances: all {J} joins (2000 pairs each) equal the oracle, with and without ASJ_LOCAL_ONLY")
