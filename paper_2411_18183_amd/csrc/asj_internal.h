@@ -44,7 +44,16 @@ __host__ __device__ inline int asj_tab_blk(int j) { return 1 + 17 * (j - 1) + 16
 #define ASJ_TAB8_EXP 0
 #define ASJ_TAB8_LOG 512
 #define ASJ_TAB8_RED 768
-#define ASJ_TAB_TOTAL_WORDS ((ASJ_NTAB16 + ASJ_NTAB8) * ASJ_TAB_WORDS)
+
+// GF(2^16) pairs read from device memory only (never copied to LDS), after
+// the GF(2^8) tables: c = alpha^(2048 j d 8^k) for components j = 1, 2,
+// octal digit k = 0..6 of a chunk's 64-chunk block index and digit value
+// d = 1..7 -- the position factor of chunks 192 and beyond (keys longer
+// than 12 KB), one pair per non-zero digit.
+#define ASJ_NTAB_HI 98
+#define ASJ_TAB_HI_BASE ((ASJ_NTAB16 + ASJ_NTAB8) * ASJ_TAB_WORDS)
+__host__ __device__ inline int asj_tab_hi(int j, int k, int d) { return (7 * (j - 1) + k) * 7 + (d - 1); }
+#define ASJ_TAB_TOTAL_WORDS ((ASJ_NTAB16 + ASJ_NTAB8 + ASJ_NTAB_HI) * ASJ_TAB_WORDS)
 
 // ---------------------------------------------------------------------------
 // Small device helpers

@@ -50,6 +50,15 @@ __global__ void tables_kernel(uint16_t *tab)
 {
     const int b = threadIdx.x; // 0..255
     const int idx = blockIdx.x;
+    if (idx > ASJ_NTAB16) { // device-memory pair h = asj_tab_hi(j, k, d)
+        const int h = idx - ASJ_NTAB16 - 1;
+        const int j = 1 + h / 49, k = (h % 49) / 7, d = 1 + h % 7;
+        const uint32_t c = gf_alpha_pow(2048ull * j * d << (3 * k), 16, kPoly16);
+        uint16_t *t = tab + ASJ_TAB_HI_BASE + h * ASJ_TAB_WORDS;
+        t[b] = (uint16_t)gf_mul((uint32_t)b, c, 16, kPoly16);
+        t[256 + b] = (uint16_t)gf_mul((uint32_t)b << 8, c, 16, kPoly16);
+        return;
+    }
     if (idx < ASJ_NTAB16) {
         const uint32_t c = gf_alpha_pow(pair_exponent(idx), 16, kPoly16);
         uint16_t *t = tab + idx * ASJ_TAB_WORDS;
@@ -81,6 +90,6 @@ __global__ void tables_kernel(uint16_t *tab)
 
 hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st)
 {
-    hipLaunchKernelGGL(tables_kernel, dim3(ASJ_NTAB16 + 1), dim3(256), 0, st, tab);
+    hipLaunchKernelGGL(tables_kernel, dim3(ASJ_NTAB16 + 1 + ASJ_NTAB_HI), dim3(256), 0, st, tab);
     return hipGetLastError();
 }

@@ -383,7 +383,7 @@ __global__ __launch_bounds__((Shape<PRESIGNED, LOCAL>::block), 4) void probe_ker
         if (PRESIGNED) {
             if (valid) sg = a.ssig[k];
         } else {
-            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, send, wst, wex, wacc, wln, tab,
+            sg = asj::sign_window<MODE, NSYM>(a.sdata, ss, ls, send, wst, wex, wacc, wln, tab, gtab,
                                               kacc2[kHi ? wave : 0], sg_hi);
         }
 

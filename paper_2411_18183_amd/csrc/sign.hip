@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
         }
         uint32_t hi = 0;
         const uint32_t v = asj::sign_window<MODE, NSYM>(data, s, len, end, kst[wave], kex[wave], kacc[wave], kown[wave], tab,
-                                                        kacc2[kHi ? wave : 0], hi);
+                                                        gtab, kacc2[kHi ? wave : 0], hi);
         if (mine) {
             out[k * stride] = v;
             if (kHi) out_hi[k * stride] = hi;

@@ -68,10 +68,26 @@ __device__ __forceinline__ uint32_t fold_group(const uint32_t *w)
     }
 }
 
+// Multiplication by alpha^(2048 J blk) for a chunk's 64-chunk block index
+// blk > 2 (keys longer than 12 KB): one device-memory pair per non-zero
+// octal digit of blk (at most seven), so that a chunk's cost does not grow
+// with its position in a long key.  Blocks 1 and 2 take the LDS pair once
+// or twice instead (the callers' loop).
+template <int J>
+__device__ __forceinline__ uint32_t scale_blk16_far(uint32_t v, const uint16_t *__restrict__ gtab, int blk)
+{
+    for (int k = 0; blk > 0; k++, blk >>= 3) {
+        const int d = blk & 7;
+        if (d) v = asj_cmul16(v, gtab + ASJ_TAB_HI_BASE + asj_tab_hi(J, k, d) * ASJ_TAB_WORDS);
+    }
+    return v;
+}
+
 // GF(2^16): components 1 and 2 of one 64-byte chunk, positions relative to
 // the chunk start; returns s1 | s2 << 16 (s2 = 0 when nsym == 1).
 template <int NSYM>
-__device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
+__device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uint16_t *__restrict__ tab,
+                                                const uint16_t *__restrict__ gtab, int c)
 {
     const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
     uint32_t a1 = 0, a2 = 0;
@@ -100,7 +116,13 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
         a2 = asj_cmul16(a2, tab + asj_tab_d0(2, d0) * ASJ_TAB_WORDS);
         a2 = asj_cmul16(a2, tab + asj_tab_d1(2, d1) * ASJ_TAB_WORDS);
     }
-    for (int blk = c >> 6; blk > 0; blk--) {
+    int blk = c >> 6;
+    if (blk > 2) {
+        a1 = scale_blk16_far<1>(a1, gtab, blk);
+        if (NSYM >= 2) a2 = scale_blk16_far<2>(a2, gtab, blk);
+        blk = 0;
+    }
+    for (; blk > 0; blk--) {
         a1 = asj_cmul16(a1, tab + asj_tab_blk(1) * ASJ_TAB_WORDS);
         if (NSYM >= 2) a2 = asj_cmul16(a2, tab + asj_tab_blk(2) * ASJ_TAB_WORDS);
     }
@@ -110,16 +132,23 @@ __device__ __forceinline__ uint32_t chunk_sig16(const uint32_t kd[16], const uin
 // Multiplication by alpha^(32 j c) for j = 1, 2 (the position factors of
 // components 1 and 2); components 3 and 4 apply them in combination.
 template <int J>
-__device__ __forceinline__ uint32_t scale16(uint32_t v, const uint16_t *__restrict__ tab, int c)
+__device__ __forceinline__ uint32_t scale16(uint32_t v, const uint16_t *__restrict__ tab,
+                                            const uint16_t *__restrict__ gtab, int c)
 {
     v = asj_cmul16(v, tab + asj_tab_d0(J, c & 7) * ASJ_TAB_WORDS);
     v = asj_cmul16(v, tab + asj_tab_d1(J, (c >> 3) & 7) * ASJ_TAB_WORDS);
-    for (int blk = c >> 6; blk > 0; blk--) v = asj_cmul16(v, tab + asj_tab_blk(J) * ASJ_TAB_WORDS);
+    int blk = c >> 6;
+    if (blk > 2) {
+        v = scale_blk16_far<J>(v, gtab, blk);
+        blk = 0;
+    }
+    for (; blk > 0; blk--) v = asj_cmul16(v, tab + asj_tab_blk(J) * ASJ_TAB_WORDS);
     return v;
 }
 
 // GF(2^16): components 3 and 4 of one 64-byte chunk; returns s3 | s4 << 16.
-__device__ __forceinline__ uint32_t chunk_sig16_hi(const uint32_t kd[16], const uint16_t *__restrict__ tab, int c)
+__device__ __forceinline__ uint32_t chunk_sig16_hi(const uint32_t kd[16], const uint16_t *__restrict__ tab,
+                                                   const uint16_t *__restrict__ gtab, int c)
 {
     const uint16_t *red = tab + ASJ_TAB_RED * ASJ_TAB_WORDS;
     uint32_t a3 = 0, a4 = 0;
@@ -134,8 +163,8 @@ __device__ __forceinline__ uint32_t chunk_sig16_hi(const uint32_t kd[16], const 
         a4 = (t4 & 0xFFFFu) ^ asj_cmul16(t4 >> 16, red);
     }
     // positions: alpha^(96c) = alpha^(32c) alpha^(64c), alpha^(128c) = (alpha^(64c))^2
-    a3 = scale16<2>(scale16<1>(a3, tab, c), tab, c);
-    a4 = scale16<2>(scale16<2>(a4, tab, c), tab, c);
+    a3 = scale16<2>(scale16<1>(a3, tab, gtab, c), tab, gtab, c);
+    a4 = scale16<2>(scale16<2>(a4, tab, gtab, c), tab, gtab, c);
     return a3 | (a4 << 16);
 }
 
@@ -185,9 +214,10 @@ __device__ __forceinline__ uint32_t chunk_plain(const uint32_t kd[16], int c)
 }
 
 template <int MODE, int NSYM>
-__device__ __forceinline__ uint32_t chunk_value(const uint32_t kd[16], const uint16_t *tab, int c)
+__device__ __forceinline__ uint32_t chunk_value(const uint32_t kd[16], const uint16_t *tab,
+                                                const uint16_t *__restrict__ gtab, int c)
 {
-    if (MODE == ASJ_MODE_SIG16) return chunk_sig16<NSYM>(kd, tab, c);
+    if (MODE == ASJ_MODE_SIG16) return chunk_sig16<NSYM>(kd, tab, gtab, c);
     if (MODE == ASJ_MODE_SIG8) return chunk_sig8<NSYM>(kd, tab, c);
     return chunk_plain(kd, c);
 }
@@ -212,16 +242,19 @@ __device__ __forceinline__ void load_tables(uint16_t *tab, const uint16_t *__res
     __syncthreads();
 }
 
-// Signature (or finalized plain hash) of each lane's key for a window of 64
-// keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes without
-// a key); end = where the relation's key bytes end (offsets[n]).  wown is
-// the wave's 64-entry LDS scratch for the pass owners.  wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with
-// four GF(2^16) components wacc2 (64 entries) accumulates the high word,
-// returned in hi.
+// Signature (or finalized plain hash) of each lane's key for a window of up
+// to 64 keys, one per lane: key bytes data[s, s + len) (len = 0 for lanes
+// without a key); end = where the relation's key bytes end (offsets[n]).
+// wown is the wave's 64-entry LDS scratch for the pass owners.
+// wst/wex/wacc are the wave's 64-entry LDS scratch arrays; with four
+// GF(2^16) components wacc2 (64 entries) accumulates the high word,
+// returned in hi.  tab: the mode's constant tables in LDS; gtab: all of
+// them in device memory (the pairs for chunks beyond the 192nd of a key).
 template <int MODE, int NSYM>
 __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data, int64_t s, int len, int64_t end,
                                                 int64_t *wst, int32_t *wex, uint32_t *wacc, int32_t *wown,
-                                                const uint16_t *tab, uint32_t *wacc2, uint32_t &hi)
+                                                const uint16_t *tab, const uint16_t *__restrict__ gtab,
+                                                uint32_t *wacc2, uint32_t &hi)
 {
     constexpr bool kHi = MODE == ASJ_MODE_SIG16 && NSYM == 4;
     const int lane = threadIdx.x % ASJ_WAVE;
@@ -242,8 +275,8 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
             const int c = x - wex[i];
             uint32_t kd[16];
             asj_load_full(data, wst[i] + (int64_t)c * ASJ_CHUNK, kd);
-            atomicXor(&wacc[i], chunk_value<MODE, NSYM>(kd, tab, c));
-            if (kHi) atomicXor(&wacc2[i], chunk_sig16_hi(kd, tab, c));
+            atomicXor(&wacc[i], chunk_value<MODE, NSYM>(kd, tab, gtab, c));
+            if (kHi) atomicXor(&wacc2[i], chunk_sig16_hi(kd, tab, gtab, c));
         }
     }
     // tail pass: lane i takes key i's last, partial chunk
@@ -252,8 +285,8 @@ __device__ __forceinline__ uint32_t sign_window(const uint8_t *__restrict__ data
     if (rem > 0) {
         uint32_t kd[16];
         asj_load_tail_fast(data, s + (int64_t)nfull * ASJ_CHUNK, rem, end, kd);
-        v = chunk_value<MODE, NSYM>(kd, tab, nfull);
-        if (kHi) vh = chunk_sig16_hi(kd, tab, nfull);
+        v = chunk_value<MODE, NSYM>(kd, tab, gtab, nfull);
+        if (kHi) vh = chunk_sig16_hi(kd, tab, gtab, nfull);
     }
     asj_wave_sync();
     v ^= wacc[lane];

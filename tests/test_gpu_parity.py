@@ -95,6 +95,20 @@ def test_signature_many_windows_and_ragged_tail(A, oracle, wl):
     assert np.array_equal(gpu_sigs(A, rel), oracle.signatures(rel))
 
 
+# Keys long enough that a chunk's 64-chunk block index has several octal
+# digits (position factors from the device-memory pairs): 12 KB (blocks up
+# to 2, the LDS pair alone), 12.3 KB, 1 MB, 3 MB and 20 MB (block index up to
+# 5120 = 0o12000), beside short keys, in an unaligned arena.
+@pytest.mark.parametrize("params", [(16, 2), (16, 4), (16, 1), (8, 2)])
+def test_signature_very_long_keys(A, oracle, wl, params):
+    rng = np.random.default_rng(sum(params))
+    lens = [12288, 12288 + 5, 3 * 4096 + 64, (1 << 20) + 3, 3 * (1 << 20) + 17, 7, 0, 20 * (1 << 20) + 1, 130]
+    keys = [rng.integers(0, 256, size=L, dtype=np.uint8).tobytes() for L in lens]
+    rel = wl.unaligned_copy(wl.from_keys(keys), 3)
+    f, nsym = params
+    assert np.array_equal(gpu_sigs(A, rel, f, nsym), oracle.signatures(rel, f, nsym))
+
+
 # Above 10240 keys the signature kernel sizes its windows from the keys'
 # mean length (4 .. 64 keys, about eight passes of 64 chunks each): mean
 # lengths chosen so that each window size is taken, with short keys and
