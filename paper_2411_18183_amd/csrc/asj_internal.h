@@ -379,18 +379,23 @@ inline int64_t asj_resident_blocks(const void *kernel, int block)
 }
 
 // Keys per signing window when the caller leaves the choice to the keys
-// (kpw = 0): the power of two in 4 .. 64 nearest (on a log scale) to
-// 32768 / mean key length, i.e. windows of about eight passes of 64 chunks
-// of 64 bytes.  Measured on the signature kernel alone, this choice came
-// within 11% of the best window size (and within 4% on average) over seven
-// sets from 32k keys of 4 KB to 1M keys of 16 bytes to 1M DNA keys of
-// 5.5 KB; windows of 64 throughout were up to 47% slower (few long keys
-// leave most compute units idle, and long windows balance poorly).
-// bytes / n is the mean key length; 46341 = 32768 * sqrt(2).
+// (kpw = 0): the power of two nearest (on a log scale) to 32768 / mean key
+// length, i.e. windows of about eight passes of 64 chunks of 64 bytes,
+// within asj_kpw_min(n) .. 64.  Measured on the signature kernel alone, this
+// choice came within 11% of the best window size (and within 4% on
+// average) over seven sets from 32k keys of 4 KB to 1M keys of 16 bytes to
+// 1M DNA keys of 5.5 KB; windows of 64 throughout were up to 47% slower
+// (few long keys leave most compute units idle, and long windows balance
+// poorly).  bytes / n is the mean key length; 46341 = 32768 * sqrt(2).
+// Sets of at most 10240 keys may go down to one key per window (a few
+// keys of a megabyte each still spread over many waves); larger sets stop
+// at four, which keeps the grid that must cover the smallest windows small.
+__host__ __device__ inline int asj_kpw_min(int64_t n) { return n <= ASJ_LOCAL_ROWS ? 1 : 4; }
 __host__ __device__ inline int asj_auto_kpw(int64_t n, int64_t bytes)
 {
+    const int lo = asj_kpw_min(n);
     int kpw = ASJ_WAVE;
-    while (kpw > 4 && 46341 * n < (int64_t)kpw * bytes) kpw >>= 1;
+    while (kpw > lo && 46341 * n < (int64_t)kpw * bytes) kpw >>= 1;
     return kpw;
 }
 

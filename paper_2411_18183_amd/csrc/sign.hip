@@ -38,11 +38,14 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
     if (has_prep) asj_batch_prep_run(prep, blockIdx.x, gridDim.x, threadIdx.x, kBlock);
     if (status && *status != 0) return; // the inputs failed validation: read no key (same for every thread)
     const int64_t end = off[n]; // the keys' bytes end here
-    if (kpw <= 0) {
-        // the grid was sized for the smallest windows; blocks beyond the
-        // chosen windows leave before they load the GF tables
-        kpw = asj_auto_kpw(n, end - off[0]);
-        if ((int64_t)blockIdx.x * kWaves * kpw >= n) return; // block-uniform
+    const int64_t bytes = end - off[0]; // both loads in flight while the tables load
+    // kpw = 0: the grid was sized for the smallest windows.  Blocks that
+    // have a window whatever the size (windows of 64 keys cover them) load
+    // the GF tables at once; the others first read the keys' extent and
+    // leave if the chosen windows do not reach them.
+    if (kpw <= 0 && (int64_t)blockIdx.x * kWaves * ASJ_WAVE >= n) { // block-uniform
+        kpw = asj_auto_kpw(n, bytes);
+        if ((int64_t)blockIdx.x * kWaves * kpw >= n) return;
     }
     __shared__ uint16_t tab[asj::TabWords<MODE>::value];
     __shared__ int64_t kst[kWaves][ASJ_WAVE];
@@ -54,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void sign_kernel(const uint8_t *__restrict_
 
     const int wave = threadIdx.x / ASJ_WAVE;
     const int lane = threadIdx.x % ASJ_WAVE;
+    if (kpw <= 0) kpw = asj_auto_kpw(n, bytes);
     const int64_t nwin = (n + kpw - 1) / kpw;
     for (int64_t w = (int64_t)blockIdx.x * kWaves + wave; w < nwin; w += (int64_t)gridDim.x * kWaves) {
         const int64_t k = w * kpw + lane;
@@ -79,11 +83,7 @@ hipError_t launch(const asj_keys *k, uint32_t *out, uint32_t *out_hi, int stride
                   const int32_t *status, const asj_batch_prep *prep, int kpw, hipStream_t st)
 {
     const asj_batch_prep none = {};
-    // sets small enough for an LDS-table join keep windows of 64 (latency-
-    // bound: each of their few blocks loads the GF tables once, and no
-    // block waits for the key bytes' extent before it does)
-    if (kpw <= 0 && k->n <= ASJ_LOCAL_ROWS) kpw = ASJ_WAVE;
-    const int kmin = kpw > 0 ? kpw : 4; // 0: the kernel picks 4 .. 64
+    const int kmin = kpw > 0 ? kpw : asj_kpw_min(k->n); // 0: the kernel picks asj_kpw_min .. 64
     const int64_t nwin = (k->n + kmin - 1) / kmin;
     int64_t blocks = (nwin + kWaves - 1) / kWaves;
     if (blocks > grid_cap) blocks = grid_cap;
