@@ -250,11 +250,16 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->kind = join_kind(o.flags);
     t->stream = st;
     t->device = dev;
-    // one stream-ordered allocation: slots | status | signatures (low, high words)
+    // one stream-ordered allocation: slots | status | signatures (low, high
+    // words) | region-build scratch
     const size_t o_status = align256(8 * (size_t)cap);
     const size_t o_sig = align256(o_status + 4);
     const size_t o_hi = align256(o_sig + 4 * (size_t)(r->n > 0 ? r->n : 1));
-    const size_t bytes = wide ? align256(o_hi + 4 * (size_t)(r->n > 0 ? r->n : 1)) : o_hi;
+    const size_t o_reg = wide ? align256(o_hi + 4 * (size_t)(r->n > 0 ? r->n : 1)) : o_hi;
+    // the table built by regions when it fits their limits (their scratch
+    // after the signatures), else by the two-pass insert
+    const int64_t region_bytes = asj_region_scratch_bytes(r->n, cap);
+    const size_t bytes = region_bytes > 0 ? o_reg + (size_t)region_bytes : o_reg;
     hipError_t e = hipMallocAsync(&t->block, bytes, st);
     if (e != hipSuccess) {
         free(t);
@@ -265,11 +270,13 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     t->status = (int32_t *)(blk + o_status);
     uint32_t *sig_r = (uint32_t *)(blk + o_sig);
     t->sig_hi = wide ? (uint32_t *)(blk + o_hi) : nullptr;
+    void *region = region_bytes > 0 ? (void *)(blk + o_reg) : nullptr;
     int out_rc = ASJ_OK;
     do {
         hipError_t le;
         tim_begin("table_init", st);
-        le = asj_launch_table_init(t->slots, cap, t->status, st);
+        le = region ? asj_launch_region_init(region, r->n, cap, t->status, st)
+                    : asj_launch_table_init(t->slots, cap, t->status, st);
         if (le == hipSuccess && t->validate) le = asj_launch_validate(r->offsets, r->n, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
@@ -279,7 +286,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
         tim_begin("insert", st);
-        le = asj_launch_insert(sig_r, r->n, plain, t->slots, (uint64_t)cap - 1, t->status, st);
+        le = region ? asj_launch_region_build(sig_r, r->n, plain, t->slots, cap, t->status, region, st)
+                    : asj_launch_insert(sig_r, r->n, plain, t->slots, (uint64_t)cap - 1, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
     } while (0);

@@ -249,7 +249,7 @@ __device__ __forceinline__ int asj_find_owner(const int32_t *ex, int x)
 // The build-side table (asj_table in the public header).
 struct asj_table {
     asj_keys r;          // borrowed build relation
-    void *block;         // one device allocation holding slots, status and the build signatures
+    void *block;         // one device allocation: slots, status, build signatures, region-build scratch
     uint64_t *slots;     // capacity slots
     int64_t capacity;    // power of two
     int32_t *status;     // device word: 0 or ASJ_ETABLEFULL
@@ -329,6 +329,19 @@ hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, 
 hipError_t asj_launch_zero2(int64_t *a, int64_t *b, hipStream_t st);
 hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
                              int32_t *status, hipStream_t st);
+// The same table built by regions of its slots (rows scattered into the
+// slots of their home region, each region then built in LDS and written
+// whole, the runs that leave a region finished with CAS).
+// asj_region_scratch_bytes gives the device scratch it needs, or -1 when the
+// table has more than 8192 regions (2^25 slots), m < 327680 or m >= 2^31:
+// then the two-pass insert builds it.
+// asj_launch_region_init replaces asj_launch_table_init (no slot is written
+// there: the build writes every slot) and sets *status = ASJ_OK;
+// asj_launch_region_build then fills slots[0 .. cap) from the signatures.
+int64_t asj_region_scratch_bytes(int64_t m, int64_t cap);
+hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st);
+hipError_t asj_launch_region_build(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, int64_t cap,
+                                   int32_t *status, void *scratch, hipStream_t st);
 
 // Per-join plan of a batch (written on the device by the plan kernel, or by
 // the host for the server).  Rows are cut into windows per join, so that no

@@ -18,6 +18,20 @@
 // The baseline simple hash join (Section 2) uses the same layout with the
 // plain key hash choosing the home slot and no signature stored (the high
 // word is zero), so its probe must compare every occupied slot it visits.
+//
+// A single table of 327680 rows or more and at most 2^25 slots is built by
+// regions instead (same layout, same probing).  Each row's (signature, row)
+// word is first scattered into the slots of the region of its home slot
+// (regions of 4096 slots; of 512 to 2048 in tables under 2^22 slots, so that
+// there are 1024), which hold that region's rows until it is built; one
+// block then reads a region's rows, places them in LDS with LDS CAS and
+// writes the region out whole, empty slots included, so the table needs no
+// fill.  The few rows whose run leaves their region, or that find its slots
+// all claimed by the partition, are placed afterwards in device memory with
+// CAS from their home slot.  Every table line is then written in order and
+// whole, instead of taking one random store and one random read per row.
+// Batches (segments sized on the device), smaller tables and the host-memory
+// join keep the two passes.
 #include "asj_internal.h"
 
 namespace {
@@ -109,6 +123,137 @@ __global__ void insert_kernel(const uint32_t *__restrict__ sig, int64_t m, uint6
     }
 }
 
+constexpr int kRegionBits = 12;   // slots per region, at most: 4096 (32 KB of LDS)
+constexpr int kRegionMinBits = 8; // slots per region, at least (tables of 256 slots and more)
+// Build rows from which the region build is used: below, its three short
+// launches cost more than the two-pass insert's random accesses (measured
+// crossover near 300000 rows at load factors 0.25 and 0.5).
+constexpr int64_t kRegionMinRows = 327680;
+constexpr int kRegionMax = 8192;  // regions per table (the LDS histogram of the partition)
+constexpr int kPartBlock = 1024;  // threads of the partition kernel
+constexpr int kPartRows = 4096;   // rows per partition block
+constexpr int kRegionBlock = 256; // threads of the region-build kernel
+constexpr int kRegionPer = (1 << kRegionBits) / kRegionBlock; // rows per thread, at most
+
+__device__ __forceinline__ uint32_t region_of(uint32_t sg, uint64_t mask, int rbits)
+{
+    return (uint32_t)((asj_mix32(sg) & mask) >> rbits);
+}
+
+// Every row's word (signature << 32 | row) into the slots of its home region,
+// which serve as that region's bucket until the region is built: a block
+// counts its rows per region in LDS, reserves each region's share with one
+// atomic, and ranks its rows within the shares in LDS.  A region's rows
+// beyond its slot count go straight to the overflow list.
+__global__ __launch_bounds__(kPartBlock) void region_scatter_kernel(const uint32_t *__restrict__ sig, int64_t m,
+                                                                    uint64_t mask, int rbits, int nreg,
+                                                                    uint32_t *__restrict__ cnt,
+                                                                    uint64_t *__restrict__ slots,
+                                                                    uint64_t *__restrict__ ovf,
+                                                                    uint32_t *__restrict__ novf,
+                                                                    const int32_t *__restrict__ status)
+{
+    if (*status != ASJ_OK) return;
+    constexpr int kPer = kPartRows / kPartBlock;
+    __shared__ uint32_t h[kRegionMax];
+    const int64_t r0 = (int64_t)blockIdx.x * kPartRows + threadIdx.x;
+    uint32_t sg[kPer], q[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int64_t r = r0 + k * kPartBlock;
+        sg[k] = r < m ? sig[r] : 0u;
+    }
+    for (int i = threadIdx.x; i < nreg; i += kPartBlock) h[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        q[k] = region_of(sg[k], mask, rbits);
+        if (r0 + k * kPartBlock < m) atomicAdd(&h[q[k]], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nreg; i += kPartBlock)
+        if (h[i]) h[i] = atomicAdd(&cnt[i], h[i]); // this block's first position in region i
+    __syncthreads();
+    const uint32_t Z = 1u << rbits;
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        const int64_t r = r0 + k * kPartBlock;
+        if (r >= m) break;
+        const uint32_t pos = atomicAdd(&h[q[k]], 1u);
+        const uint64_t e = ((uint64_t)sg[k] << 32) | (uint32_t)r;
+        if (pos < Z) slots[((uint64_t)q[k] << rbits) + pos] = e;
+        else ovf[atomicAdd(novf, 1u)] = e;
+    }
+}
+
+// Region q's rows (the first min(cnt[q], 2^rbits) words of its slots) placed
+// by linear probing in LDS with CAS, then the region written out whole,
+// empty slots included; a row that finds every slot from its home to the
+// region's end taken goes to the overflow list.
+__global__ __launch_bounds__(kRegionBlock) void region_build_kernel(const uint32_t *__restrict__ cnt, int nreg,
+                                                                    int rbits, uint64_t mask, int plain,
+                                                                    uint64_t *__restrict__ slots,
+                                                                    uint64_t *__restrict__ ovf,
+                                                                    uint32_t *__restrict__ novf,
+                                                                    const int32_t *__restrict__ status)
+{
+    // A failed validation leaves the rows out but still writes every region
+    // (empty), so that the table is defined whatever its status.
+    const bool ok = *status == ASJ_OK;
+    __shared__ unsigned long long tab[1 << kRegionBits];
+    const uint32_t Z = 1u << rbits;
+    for (int q = blockIdx.x; q < nreg; q += gridDim.x) { // block-uniform
+        const uint64_t base = (uint64_t)q << rbits;
+        const uint32_t c = ok ? min(cnt[q], Z) : 0u;
+        uint64_t e[kRegionPer];
+#pragma unroll
+        for (int k = 0; k < kRegionPer; k++) {
+            const uint32_t i = threadIdx.x + k * kRegionBlock;
+            e[k] = i < c ? slots[base + i] : 0ull;
+        }
+        for (uint32_t i = threadIdx.x; i < Z; i += kRegionBlock) tab[i] = ASJ_EMPTY_SLOT;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRegionPer; k++) {
+            if (threadIdx.x + k * kRegionBlock >= c) break;
+            const uint32_t sg = (uint32_t)(e[k] >> 32);
+            const unsigned long long val = plain ? (unsigned long long)(uint32_t)e[k] : (unsigned long long)e[k];
+            uint32_t h = (uint32_t)((asj_mix32(sg) & mask) - base);
+            while (h < Z && atomicCAS(&tab[h], (unsigned long long)ASJ_EMPTY_SLOT, val) != ASJ_EMPTY_SLOT) h++;
+            if (h == Z) ovf[atomicAdd(novf, 1u)] = e[k];
+        }
+        __syncthreads(); // every row read and placed
+        for (uint32_t i = threadIdx.x; i < Z; i += kRegionBlock) slots[base + i] = tab[i];
+        __syncthreads(); // the next region reuses tab
+    }
+}
+
+// The overflow rows, once every region is written: linear probing with CAS
+// in device memory from the home slot, wrapping at the table's end.  A row
+// moved here by the partition (its region had more rows than slots) never
+// saw its region, which may still hold empty slots after its home.
+__global__ void region_overflow_kernel(const uint64_t *__restrict__ ovf, const uint32_t *__restrict__ novf,
+                                       uint64_t mask, int plain, uint64_t *__restrict__ slots,
+                                       int32_t *__restrict__ status)
+{
+    const uint32_t n = *novf;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t e = ovf[i];
+        const uint32_t sg = (uint32_t)(e >> 32);
+        const unsigned long long val = plain ? (unsigned long long)(uint32_t)e : (unsigned long long)e;
+        uint64_t h = asj_mix32(sg) & mask;
+        for (uint64_t tries = 0;; h++) {
+            if (++tries > mask) { // every slot taken
+                atomicExch(status, (int32_t)ASJ_ETABLEFULL);
+                break;
+            }
+            const unsigned long long old = atomicCAS((unsigned long long *)&slots[h & mask],
+                                                     (unsigned long long)ASJ_EMPTY_SLOT, val);
+            if (old == ASJ_EMPTY_SLOT) break;
+        }
+    }
+}
+
 int grid_for(int64_t n, int block, int cap)
 {
     int64_t g = (n + block - 1) / block;
@@ -180,5 +325,68 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
         hipLaunchKernelGGL((insert_kernel<0, 1>), g, b, 0, st, sig, m, slots, mask, status);
         hipLaunchKernelGGL((insert_kernel<0, 0>), g, b, 0, st, sig, m, slots, mask, status);
     }
+    return hipGetLastError();
+}
+
+namespace {
+struct region_layout {
+    int rbits, nreg;
+    uint32_t *novf, *cnt;
+    uint64_t *ovf;
+    int64_t bytes;
+};
+
+// The scratch of a region build: overflow count | region counts (nreg
+// words) | overflow list (m words).
+bool region_plan(int64_t m, int64_t cap, uint8_t *p, region_layout *L)
+{
+    if (cap < 64 || (cap & (cap - 1)) || m < kRegionMinRows || m >= ((int64_t)1 << 31)) return false;
+    // regions of 4096 slots, smaller for tables under 2^22 slots (at least
+    // 1024 regions then, each of at least 256 slots or the whole table)
+    const int lg = __builtin_ctzll((unsigned long long)cap);
+    L->rbits = std::max(std::min(lg - 10, kRegionBits), std::min(lg, kRegionMinBits));
+    const int64_t nreg = cap >> L->rbits;
+    if (nreg > kRegionMax) return false;
+    L->nreg = (int)nreg;
+    const int64_t o_ovf = 256 + ((4 * nreg + 255) & ~(int64_t)255);
+    L->bytes = o_ovf + 8 * (m > 0 ? m : 1);
+    L->novf = (uint32_t *)p;
+    L->cnt = (uint32_t *)(p + 256);
+    L->ovf = (uint64_t *)(p + o_ovf);
+    return true;
+}
+
+int region_grid(int nreg) { return std::min(nreg, 2048); }
+} // namespace
+
+int64_t asj_region_scratch_bytes(int64_t m, int64_t cap)
+{
+    region_layout L;
+    return region_plan(m, cap, nullptr, &L) ? L.bytes : -1;
+}
+
+hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st)
+{
+    region_layout L;
+    if (!scratch || !region_plan(m, cap, (uint8_t *)scratch, &L)) return hipErrorInvalidValue;
+    return asj_launch_local_init((int64_t *)L.novf, nullptr, status, L.cnt, L.nreg, st);
+}
+
+hipError_t asj_launch_region_build(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, int64_t cap,
+                                   int32_t *status, void *scratch, hipStream_t st)
+{
+    region_layout L;
+    if (!scratch || !region_plan(m, cap, (uint8_t *)scratch, &L)) return hipErrorInvalidValue;
+    const uint64_t mask = (uint64_t)cap - 1;
+    const int pb = (int)((m + kPartRows - 1) / kPartRows);
+    if (pb > 0)
+        hipLaunchKernelGGL(region_scatter_kernel, dim3(pb), dim3(kPartBlock), 0, st, sig, m, mask, L.rbits, L.nreg,
+                           L.cnt, slots, L.ovf, L.novf, (const int32_t *)status);
+    hipLaunchKernelGGL(region_build_kernel, dim3(region_grid(L.nreg)), dim3(kRegionBlock), 0, st,
+                       (const uint32_t *)L.cnt, L.nreg, L.rbits, mask, plain, slots, L.ovf, L.novf,
+                       (const int32_t *)status);
+    if (pb > 0)
+        hipLaunchKernelGGL(region_overflow_kernel, dim3(64), dim3(256), 0, st, (const uint64_t *)L.ovf,
+                           (const uint32_t *)L.novf, mask, plain, slots, status);
     return hipGetLastError();
 }

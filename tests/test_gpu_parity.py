@@ -602,6 +602,61 @@ def test_right_outer_probe_calls_report_their_own_unmatched_rows(A, oracle, wl):
     t.free()
 
 
+def region_case(wl, case):
+    """A build side, its load factor, and a probe side holding every distinct
+    build key once (so that a build row missing from the table loses its
+    pair) plus 2000 random keys."""
+    rng = np.random.default_rng(sum(map(ord, case)))
+
+    def rand(k):
+        lens = rng.integers(1, 24, size=k)
+        off = np.zeros(k + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, size=int(off[-1]), dtype=np.uint8).tobytes()
+        return [data[off[i]:off[i + 1]] for i in range(k)]
+
+    rk, lf = {
+        # region builds (327680 rows or more)
+        "nearly_full": lambda: (rand(524000), 0.9999),                       # 2^19 slots, 512-slot regions
+        "one_key": lambda: ([b"same key"] * 6000 + rand(334000), 0.3),       # 2048-slot regions
+        "one_key_sparse": lambda: ([b"same key"] * 6000 + rand(334000), 0.08),  # 2^23 slots, 4096-slot regions
+        # two-pass builds
+        "small_nearly_full": lambda: (rand(16383), 0.9999),
+        "small_one_key": lambda: ([b"same key"] * 6000 + rand(3000), 0.5),
+        "empty": lambda: ([], 0.5),
+    }[case]()
+    uniq = list(dict.fromkeys(rk))
+    sk = [uniq[i] for i in rng.permutation(len(uniq))] + rand(2000)
+    return wl.from_keys(rk), wl.from_keys(sk), lf
+
+
+_REGION_CASES = {}  # case -> relations, load factor and the oracle's join
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("sched", ["split", "fused_global"])
+@pytest.mark.parametrize("case", ["nearly_full", "one_key", "one_key_sparse", "small_nearly_full", "small_one_key",
+                                  "empty"])
+def test_device_table_every_row_found(A, oracle, wl, case, sched, plain):
+    """Device-memory tables of 327680 build rows or more are built region by
+    region (rows grouped by the region of their home slot, each region placed
+    in LDS); rows whose run leaves their region, or that find its slots all
+    taken by others homed there, are placed from their home slot in device
+    memory, past the table's end at slot 0.  Smaller tables take the
+    two-pass insert.  Nearly full tables, a key repeated beyond a region's
+    slots and an empty build side must give the oracle's join and, with
+    signatures, its candidate count, with every build key probed."""
+    if case not in _REGION_CASES:
+        R, S, lf = region_case(wl, case)
+        _REGION_CASES[case] = (R, S, lf, oracle.join_signature(R, S))
+    R, S, lf, (want, want_cand) = _REGION_CASES[case]
+    flags = A.ASJ_PLAIN if plain else 0
+    got, total, ncand = gpu_join(A, R, S, sched=sched, flags=flags, load_factor=lf)
+    assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)
+    if not plain:
+        assert ncand == want_cand
+
+
 @pytest.mark.parametrize("m", [10239, 10240, 10241])
 def test_single_join_at_the_lds_table_limit(A, oracle, wl, m):
     """asj_join with one build row below, at and above the LDS-table limit
