@@ -418,8 +418,8 @@ int table_free_impl(asj_table *t)
 
 // ---- batch workspace layout (each part 256-byte aligned) ----
 struct BatchLayout {
-    size_t desc, rows_done, tot, status, win_r, win_s, win_l, rmatch, sig, ssig, slots, bytes;
-    int64_t slot_bound, win_r_cap, win_s_cap;
+    size_t desc, rows_done, tot, status, win_r, win_s, win_l, rmatch, sig, ssig, slots, rcnt, rmap, novf, ovf, bytes;
+    int64_t slot_bound, win_r_cap, win_s_cap, region_cap;
 };
 
 bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf, BatchLayout *L)
@@ -430,13 +430,15 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     // sum over joins of ceil(rows_j / w) <= rows / w + J
     L->win_r_cap = n_build / ASJ_WAVE + J + 1;
     L->win_s_cap = n_probe / kpw + J + 1;
+    // table regions of 64 slots or more each
+    L->region_cap = L->slot_bound / 64 + 1;
     size_t off = 0;
     L->desc = off;
     off = align256(off + sizeof(asj_join_desc) * (size_t)J);
     L->rows_done = off;
     off = align256(off + sizeof(int64_t) * (size_t)J);
     L->tot = off;
-    off = align256(off + 4 * sizeof(uint64_t));
+    off = align256(off + 5 * sizeof(uint64_t));
     L->status = off;
     off = align256(off + sizeof(int32_t));
     L->win_r = off;
@@ -453,6 +455,15 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     off = align256(off + sizeof(uint32_t) * (size_t)(n_probe > 0 ? n_probe : 1));
     L->slots = off;
     off = align256(off + sizeof(uint64_t) * (size_t)L->slot_bound);
+    // build by regions: region counts, region -> join, overflow count and list
+    L->rcnt = off;
+    off = align256(off + sizeof(uint32_t) * (size_t)L->region_cap);
+    L->rmap = off;
+    off = align256(off + sizeof(int32_t) * (size_t)L->region_cap);
+    L->novf = off;
+    off = align256(off + sizeof(uint64_t));
+    L->ovf = off;
+    off = align256(off + sizeof(uint64_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->bytes = off;
     return true;
 }
@@ -851,30 +862,37 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     uint32_t *sig_r = (uint32_t *)(ws + L.sig);
     uint32_t *sig_s = (uint32_t *)(ws + L.ssig);
     uint64_t *slots = (uint64_t *)(ws + L.slots);
+    uint32_t *rcnt = (uint32_t *)(ws + L.rcnt);
+    int32_t *rmap = (int32_t *)(ws + L.rmap);
+    uint64_t *novf = (uint64_t *)(ws + L.novf);
+    uint64_t *ovf = (uint64_t *)(ws + L.ovf);
     int out_rc = ASJ_OK;
     do {
         hipError_t e;
         tim_begin("batch_plan", st);
         e = asj_launch_batch_plan(b->r_seg, b->s_seg, b->njoins, b->r.n, b->s.n, L.slot_bound, lf, kpw,
                                   local ? ASJ_LOCAL_ROWS : -1, local_only, desc, rows_done, b->out_count,
-                                  b->cand_count, b->done_clock, tot, status, st);
+                                  b->cand_count, b->done_clock, tot, status, local_only ? nullptr : rcnt,
+                                  L.region_cap, novf, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->r.offsets, b->r.n, status, st);
         if (e == hipSuccess && validate) e = asj_launch_validate(b->s.offsets, b->s.n, status, st);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
-        // the slot fill and window maps are written by the signature kernel
-        // (or, without build keys, a kernel of their own)
+        // the window and region maps are written by the signature kernel
+        // (or, without build keys, a kernel of their own); the segments are
+        // built by regions, which write every slot (no fill)
         uint8_t *rmatch = asj_kind_marks_build(kind) ? ws + L.rmatch : nullptr;
-        asj_batch_prep prep = {slots, L.slot_bound, tot, desc, b->s_seg, b->njoins, kpw,
+        asj_batch_prep prep = {tot, desc, b->s_seg, b->njoins, kpw,
                                win_r, L.win_r_cap, win_s, L.win_s_cap, win_l, L.win_s_cap,
-                               (uint32_t *)rmatch, rmatch ? (b->r.n + 3) / 4 : 0};
+                               (uint32_t *)rmatch, rmatch ? (b->r.n + 3) / 4 : 0, rmap, L.region_cap};
         tim_begin(plain ? "hash_build" : "sign_build", st);
         e = launch_sign_for(&b->r, sig, plain, sig_r, g_dev[dev].tab, st, status, nullptr, 1, &prep, 0);
         tim_end(st);
         if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         if (!local_only) { // otherwise no join has a device-memory table
             tim_begin("insert", st);
-            e = asj_launch_insert_batch(sig_r, b->r.n, b->r_seg, desc, win_r, tot, L.win_r_cap, slots, status, st);
+            e = asj_launch_region_build_batch(sig_r, b->r.n, b->r_seg, b->njoins, desc, win_r, tot, L.win_r_cap,
+                                              rmap, L.region_cap, rcnt, ovf, novf, slots, status, st);
             tim_end(st);
             if (e != hipSuccess) { out_rc = hip_fail(e); break; }
         }

@@ -309,7 +309,7 @@ hipError_t asj_launch_tables(uint16_t *tab, hipStream_t st);
 // out[k * stride] = signature (plain hash) of key k; with four GF(2^16)
 // components that is the low word (components 1, 2) and out_hi[k * stride]
 // receives the high word (components 3, 4).
-// prep (may be NULL): the batch's slot fill and window maps, written by the
+// prep (may be NULL): the batch's window and region maps, written by the
 // kernel's blocks before they sign (one launch fewer per batch).
 // kpw: keys per signing window (1 .. 64), or 0 for asj_auto_kpw's choice
 // from the keys' mean length, made by the kernel.
@@ -368,7 +368,16 @@ struct asj_join_desc {
     int64_t wbase;   // first probe window of the join (device-memory table)
     int64_t wbase_r; // first build window of the join (device-memory table)
     int64_t wbase_l; // first probe window of the join (LDS table)
+    int64_t rbase;   // first table region of the join's segment (batch tables built by regions)
 };
+
+// Slots per table region of a batch segment of `cap` slots (a power of two,
+// at least 64), as a power of two: the whole segment up to 4096 slots.
+__host__ __device__ inline int asj_seg_region_bits(uint64_t cap)
+{
+    const int b = 63 - __builtin_clzll((unsigned long long)cap);
+    return b < 12 ? b : 12;
+}
 
 // Batches: a join with at most this many build rows is probed against a
 // table that each probing block builds in LDS from the build signatures
@@ -412,15 +421,14 @@ __host__ __device__ inline int asj_auto_kpw(int64_t n, int64_t bytes)
     return kpw;
 }
 
-// A batch's preparation after its plan: empty slots up to the planned total,
-// then the window maps (block b writes the windows of joins b, b + nblocks,
-// ...): build window -> join, for every probe window its join, first row and
-// row count, and LDS-table probe window -> join.  Every write stays inside
-// the capacities whatever the segment arrays hold.
+// A batch's preparation after its plan: the window and region maps (block b
+// writes those of joins b, b + nblocks, ...): build window -> join, for every
+// probe window its join, first row and row count, LDS-table probe window ->
+// join, and table region -> join.  Every write stays inside the capacities
+// whatever the segment arrays hold.  (No slot is written: the segments are
+// built by regions, which write every slot.)
 struct asj_batch_prep {
-    uint64_t *slots;
-    int64_t slot_cap;
-    const uint64_t *tot; // planned totals: slots, build windows, probe windows, LDS-table windows
+    const uint64_t *tot; // planned totals: slots, build windows, probe windows, LDS-table windows, regions
     const asj_join_desc *desc;
     const int64_t *s_seg;
     int32_t njoins;
@@ -433,25 +441,28 @@ struct asj_batch_prep {
     int64_t win_l_cap;
     uint32_t *rmatch;     // right and full outer joins: the matched-row bytes, zeroed here
     int64_t rmatch_words; // in 4-byte words
+    int32_t *rmap;        // table region -> join
+    int64_t rmap_cap;
 };
 
 __device__ inline void asj_batch_prep_run(const asj_batch_prep &p, int64_t block, int64_t nblocks, int tid,
                                           int nthreads)
 {
-    const int64_t n = p.slot_cap < (int64_t)p.tot[0] ? p.slot_cap : (int64_t)p.tot[0];
-    for (int64_t i = block * nthreads + tid; i < n; i += nblocks * nthreads) p.slots[i] = ASJ_EMPTY_SLOT;
     if (p.rmatch)
         for (int64_t i = block * nthreads + tid; i < p.rmatch_words; i += nblocks * nthreads) p.rmatch[i] = 0u;
     const int64_t nr = p.win_r_cap < (int64_t)p.tot[1] ? p.win_r_cap : (int64_t)p.tot[1];
     const int64_t ns = p.win_s_cap < (int64_t)p.tot[2] ? p.win_s_cap : (int64_t)p.tot[2];
     const int64_t nl = p.win_l_cap < (int64_t)p.tot[3] ? p.win_l_cap : (int64_t)p.tot[3];
+    const int64_t nq = p.rmap_cap < (int64_t)p.tot[4] ? p.rmap_cap : (int64_t)p.tot[4];
     for (int64_t j = block; j < p.njoins; j += nblocks) {
         const asj_join_desc d = p.desc[j];
         const int64_t r1 = j + 1 < p.njoins ? p.desc[j + 1].wbase_r : nr;
         const int64_t s1 = j + 1 < p.njoins ? p.desc[j + 1].wbase : ns;
         const int64_t l1 = j + 1 < p.njoins ? p.desc[j + 1].wbase_l : nl;
+        const int64_t q1 = j + 1 < p.njoins ? p.desc[j + 1].rbase : nq;
         const int64_t first = p.s_seg[j], end = p.s_seg[j + 1];
         for (int64_t w = d.wbase_r + tid; w < (r1 < nr ? r1 : nr); w += nthreads) p.win_r[w] = (int32_t)j;
+        for (int64_t q = d.rbase + tid; q < (q1 < nq ? q1 : nq); q += nthreads) p.rmap[q] = (int32_t)j;
         for (int64_t w = d.wbase_l + tid; w < (l1 < nl ? l1 : nl); w += nthreads) p.win_l[w] = (int32_t)j;
         for (int64_t w = d.wbase + tid; w < (s1 < ns ? s1 : ns); w += nthreads) {
             asj_win e;
@@ -544,14 +555,26 @@ hipError_t asj_launch_sort_pairs(asj_pair *pairs, const int64_t *count, int64_t 
 hipError_t asj_launch_read(const void *src, int64_t bytes, uint32_t *out, int grid, hipStream_t st);
 
 // Batch: per-join segment plan (capacities, prefix offsets, counters, start
-// clock), slot initialisation up to the planned total, batched inserts.
+// clock), the preparation (window and region maps), the build by regions.
 // tot[0] = slots of all segments, tot[1] = build windows, tot[2] = probe
-// windows; win_r / win_s map windows to joins.
+// windows, tot[3] = LDS-table probe windows, tot[4] = table regions (of
+// asj_seg_region_bits slots each); win_r / win_s map windows to joins.  With
+// rcnt, the plan also clears rcnt[0 .. tot[4]) (at most rcnt_cap words) and
+// *novf, the region counts and overflow count of a build by regions.
 hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int32_t njoins, int64_t n_r, int64_t n_s,
                                  int64_t slot_cap, float load_factor, int keys_per_window, int64_t local_rows,
                                  int local_only, asj_join_desc *desc, int64_t *rows_done, int64_t *out_count, int64_t *cand_count,
-                                 uint64_t *done_clock, uint64_t *tot, int32_t *status, hipStream_t st);
+                                 uint64_t *done_clock, uint64_t *tot, int32_t *status, uint32_t *rcnt, int64_t rcnt_cap,
+                                 uint64_t *novf, hipStream_t st);
 hipError_t asj_launch_batch_prep(const asj_batch_prep *p, hipStream_t st);
-hipError_t asj_launch_insert_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, const asj_join_desc *desc,
-                                   const int32_t *win_r, const uint64_t *tot, int64_t win_r_cap, uint64_t *slots,
-                                   int32_t *status, hipStream_t st);
+// The batch's segments built by regions, as a single table of 327680 rows or
+// more is (every slot written, so no fill): the build rows' words scattered
+// into their home regions (a block per 64 build windows), every region
+// (rmap: region -> join, written by the preparation) built in LDS and
+// written whole, then the rows that left their region.  rcnt and *novf must
+// be zero (the plan clears them); ovf holds m words.
+hipError_t asj_launch_region_build_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, int32_t njoins,
+                                         const asj_join_desc *desc, const int32_t *win_r, const uint64_t *tot,
+                                         int64_t win_r_cap, const int32_t *rmap, int64_t rmap_cap, uint32_t *rcnt,
+                                         uint64_t *ovf, uint64_t *novf, uint64_t *slots, int32_t *status,
+                                         hipStream_t st);

@@ -179,6 +179,7 @@ int launch_batch(asj_server *S, Slot &sl, const std::vector<Req *> &batch)
         h_desc[j].wbase = wb;
         h_desc[j].wbase_r = 0;
         h_desc[j].wbase_l = 0;
+        h_desc[j].rbase = 0;
         const int64_t nw = (r->n + kpw - 1) / kpw;
         for (int64_t w = 0; w < nw; w++) {
             h_win[wb + w].join = j;

@@ -15,7 +15,7 @@ constexpr int kWaves = kBlock / ASJ_WAVE;
 // (DNA keys 10% slower); four and eight rounds came within 2% of each
 // other on every set but 1M keys of 64 bytes (eight: 7%, 1.5 us slower)
 // and 1M DNA keys (eight: 2% faster), and the batch whose blocks also
-// write the slot fill and window maps (256 joins, 6.3M build keys) signed
+// wrote the slot fill and window maps (256 joins, 6.3M build keys) signed
 // 6% slower on four rounds than on eight.
 constexpr int kSignRounds = 8;
 

@@ -186,25 +186,110 @@ __global__ __launch_bounds__(kPartBlock) void region_scatter_kernel(const uint32
     }
 }
 
-// Region q's rows (the first min(cnt[q], 2^rbits) words of its slots) placed
-// by linear probing in LDS with CAS, then the region written out whole,
-// empty slots included; a row that finds every slot from its home to the
-// region's end taken goes to the overflow list.
-__global__ __launch_bounds__(kRegionBlock) void region_build_kernel(const uint32_t *__restrict__ cnt, int nreg,
+// The build rows of a batch into the slots of their home region, each
+// region of a join's segment holding 2^asj_seg_region_bits slots.  A block
+// takes 64 consecutive build windows (64 rows of one join each, so 4096 rows
+// of one or more joins, whose regions are numbered consecutively): it counts
+// its rows per region in LDS, reserves each region's share with one device
+// atomic, and ranks its rows within the shares in LDS.  Regions more than
+// kRegionMax past the block's first one (windows of several joins with very
+// large segments) take one device atomic per row instead.
+constexpr int kScatterWins = kPartRows / ASJ_WAVE; // build windows per block
+
+__global__ __launch_bounds__(kPartBlock) void region_scatter_batch_kernel(
+    const uint32_t *__restrict__ sig, int64_t m, const int64_t *__restrict__ r_seg,
+    const asj_join_desc *__restrict__ desc, const int32_t *__restrict__ win_r, const uint64_t *__restrict__ tot,
+    int64_t win_cap, uint32_t *__restrict__ rcnt, uint64_t *__restrict__ slots, uint64_t *__restrict__ ovf,
+    uint32_t *__restrict__ novf, const int32_t *__restrict__ status)
+{
+    if (*status != ASJ_OK) return; // same value for every thread
+    constexpr int kPer = kScatterWins / (kPartBlock / ASJ_WAVE); // windows per wave
+    __shared__ uint32_t h[kRegionMax];
+    const int64_t nw = min(win_cap, (int64_t)tot[1]);
+    const int64_t w0 = (int64_t)blockIdx.x * kScatterWins;
+    if (w0 >= nw) return; // block-uniform
+    const int64_t rlo = desc[win_r[w0]].rbase;
+    const int lane = threadIdx.x % ASJ_WAVE, wave = threadIdx.x / ASJ_WAVE;
+    int64_t reg[kPer];   // the row's region, or -1
+    uint64_t e[kPer];    // its word (signature << 32 | row)
+    uint64_t sbase[kPer]; // first slot of its region
+    uint32_t Zk[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        reg[k] = -1;
+        const int64_t w = w0 + wave * kPer + k;
+        if (w >= nw) continue;
+        const int j = __builtin_amdgcn_readfirstlane(win_r[w]);
+        const int64_t lo = r_seg[j], hi = min(r_seg[j + 1], m);
+        const asj_join_desc d = desc[j];
+        const int64_t g = lo + (w - d.wbase_r) * ASJ_WAVE + lane;
+        if (g < lo || g >= hi) continue;
+        const uint32_t sg = sig[g];
+        const int rb = asj_seg_region_bits(d.mask + 1);
+        const uint64_t q = (asj_mix32(sg) & d.mask) >> rb;
+        reg[k] = d.rbase + (int64_t)q;
+        e[k] = ((uint64_t)sg << 32) | (uint32_t)g;
+        sbase[k] = d.tbase + (q << rb);
+        Zk[k] = 1u << rb;
+    }
+    for (int i = threadIdx.x; i < kRegionMax; i += kPartBlock) h[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; k++)
+        if (reg[k] >= 0 && reg[k] - rlo < kRegionMax) atomicAdd(&h[reg[k] - rlo], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kRegionMax; i += kPartBlock)
+        if (h[i]) h[i] = atomicAdd(&rcnt[rlo + i], h[i]); // this block's first position in region rlo + i
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+        if (reg[k] < 0) continue;
+        const uint32_t pos = reg[k] - rlo < kRegionMax ? atomicAdd(&h[reg[k] - rlo], 1u) : atomicAdd(&rcnt[reg[k]], 1u);
+        if (pos < Zk[k]) slots[sbase[k] + pos] = e[k];
+        else ovf[atomicAdd(novf, 1u)] = e[k];
+    }
+}
+
+// Region r's rows (the first min(cnt[r], its slot count) words of its
+// slots) placed by linear probing in LDS with CAS, then the region written
+// out whole, empty slots included; a row that finds every slot from its home
+// to the region's end taken goes to the overflow list.  A single table: the
+// regions of 2^rbits slots of slots[0 .. nreg << rbits); a batch (BATCH):
+// region r of the join rmap[r], the regions of each segment numbered from
+// the join's rbase.
+template <int BATCH>
+__global__ __launch_bounds__(kRegionBlock) void region_build_kernel(const uint32_t *__restrict__ cnt, int64_t nreg,
                                                                     int rbits, uint64_t mask, int plain,
+                                                                    const uint64_t *__restrict__ tot,
+                                                                    const int32_t *__restrict__ rmap,
+                                                                    const asj_join_desc *__restrict__ desc,
                                                                     uint64_t *__restrict__ slots,
                                                                     uint64_t *__restrict__ ovf,
                                                                     uint32_t *__restrict__ novf,
                                                                     const int32_t *__restrict__ status)
 {
-    // A failed validation leaves the rows out but still writes every region
-    // (empty), so that the table is defined whatever its status.
+    // A single table whose validation failed still gets every region
+    // written (empty), so that it is defined whatever its status; a batch
+    // whose plan or validation failed is left alone (its probe does nothing).
     const bool ok = *status == ASJ_OK;
+    if (BATCH) {
+        if (!ok) return;
+        nreg = min(nreg, (int64_t)tot[4]);
+    }
     __shared__ unsigned long long tab[1 << kRegionBits];
-    const uint32_t Z = 1u << rbits;
-    for (int q = blockIdx.x; q < nreg; q += gridDim.x) { // block-uniform
-        const uint64_t base = (uint64_t)q << rbits;
-        const uint32_t c = ok ? min(cnt[q], Z) : 0u;
+    for (int64_t r = blockIdx.x; r < nreg; r += gridDim.x) { // block-uniform
+        uint64_t tb = 0, q = (uint64_t)r;
+        if (BATCH) {
+            const asj_join_desc d = desc[rmap[r]];
+            tb = d.tbase;
+            mask = d.mask;
+            rbits = asj_seg_region_bits(d.mask + 1);
+            q = (uint64_t)(r - d.rbase);
+        }
+        const uint32_t Z = 1u << rbits;
+        const uint64_t home0 = q << rbits; // the region's first slot within its table
+        const uint64_t base = tb + home0;
+        const uint32_t c = ok ? min(cnt[r], Z) : 0u;
         uint64_t e[kRegionPer];
 #pragma unroll
         for (int k = 0; k < kRegionPer; k++) {
@@ -218,7 +303,7 @@ __global__ __launch_bounds__(kRegionBlock) void region_build_kernel(const uint32
             if (threadIdx.x + k * kRegionBlock >= c) break;
             const uint32_t sg = (uint32_t)(e[k] >> 32);
             const unsigned long long val = plain ? (unsigned long long)(uint32_t)e[k] : (unsigned long long)e[k];
-            uint32_t h = (uint32_t)((asj_mix32(sg) & mask) - base);
+            uint32_t h = (uint32_t)((asj_mix32(sg) & mask) - home0);
             while (h < Z && atomicCAS(&tab[h], (unsigned long long)ASJ_EMPTY_SLOT, val) != ASJ_EMPTY_SLOT) h++;
             if (h == Z) ovf[atomicAdd(novf, 1u)] = e[k];
         }
@@ -229,28 +314,40 @@ __global__ __launch_bounds__(kRegionBlock) void region_build_kernel(const uint32
 }
 
 // The overflow rows, once every region is written: linear probing with CAS
-// in device memory from the home slot, wrapping at the table's end.  A row
-// moved here by the partition (its region had more rows than slots) never
-// saw its region, which may still hold empty slots after its home.
+// in device memory from the home slot, wrapping at the table's (segment's)
+// end.  A row moved here by the partition (its region had more rows than
+// slots) never saw its region, which may still hold empty slots after its
+// home.  A batch finds each row's join from the build segments.
+template <int BATCH>
 __global__ void region_overflow_kernel(const uint64_t *__restrict__ ovf, const uint32_t *__restrict__ novf,
-                                       uint64_t mask, int plain, uint64_t *__restrict__ slots,
+                                       uint64_t mask, int plain, const int64_t *__restrict__ r_seg, int32_t njoins,
+                                       const asj_join_desc *__restrict__ desc, uint64_t *__restrict__ slots,
                                        int32_t *__restrict__ status)
 {
+    if (*status != ASJ_OK) return; // a failed plan or validation leaves the overflow count unset
     const uint32_t n = *novf;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint64_t e = ovf[i];
         const uint32_t sg = (uint32_t)(e >> 32);
         const unsigned long long val = plain ? (unsigned long long)(uint32_t)e : (unsigned long long)e;
-        uint64_t h = asj_mix32(sg) & mask;
-        for (uint64_t tries = 0;; h++) {
-            if (++tries > mask) { // every slot taken
-                atomicExch(status, (int32_t)ASJ_ETABLEFULL);
-                break;
+        uint64_t tb = 0;
+        if (BATCH) { // the last join whose rows start at or before row g: the one holding g
+            const int64_t g = (int64_t)(uint32_t)e;
+            int lo = 0, hi = njoins - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (r_seg[mid] <= g) lo = mid;
+                else hi = mid - 1;
             }
-            const unsigned long long old = atomicCAS((unsigned long long *)&slots[h & mask],
-                                                     (unsigned long long)ASJ_EMPTY_SLOT, val);
-            if (old == ASJ_EMPTY_SLOT) break;
+            tb = desc[lo].tbase;
+            mask = desc[lo].mask;
         }
+        const uint64_t home = asj_mix32(sg) & mask;
+        bool placed = false;
+        for (uint64_t t = 0; t <= mask && !placed; t++) // every slot of the table once
+            placed = atomicCAS((unsigned long long *)&slots[tb + ((home + t) & mask)],
+                               (unsigned long long)ASJ_EMPTY_SLOT, val) == ASJ_EMPTY_SLOT;
+        if (!placed) atomicExch(status, (int32_t)ASJ_ETABLEFULL);
     }
 }
 
@@ -382,11 +479,35 @@ hipError_t asj_launch_region_build(const uint32_t *sig, int64_t m, int plain, ui
     if (pb > 0)
         hipLaunchKernelGGL(region_scatter_kernel, dim3(pb), dim3(kPartBlock), 0, st, sig, m, mask, L.rbits, L.nreg,
                            L.cnt, slots, L.ovf, L.novf, (const int32_t *)status);
-    hipLaunchKernelGGL(region_build_kernel, dim3(region_grid(L.nreg)), dim3(kRegionBlock), 0, st,
-                       (const uint32_t *)L.cnt, L.nreg, L.rbits, mask, plain, slots, L.ovf, L.novf,
+    hipLaunchKernelGGL(region_build_kernel<0>, dim3(region_grid(L.nreg)), dim3(kRegionBlock), 0, st,
+                       (const uint32_t *)L.cnt, (int64_t)L.nreg, L.rbits, mask, plain, (const uint64_t *)nullptr,
+                       (const int32_t *)nullptr, (const asj_join_desc *)nullptr, slots, L.ovf, L.novf,
                        (const int32_t *)status);
     if (pb > 0)
-        hipLaunchKernelGGL(region_overflow_kernel, dim3(64), dim3(256), 0, st, (const uint64_t *)L.ovf,
-                           (const uint32_t *)L.novf, mask, plain, slots, status);
+        hipLaunchKernelGGL(region_overflow_kernel<0>, dim3(64), dim3(256), 0, st, (const uint64_t *)L.ovf,
+                           (const uint32_t *)L.novf, mask, plain, (const int64_t *)nullptr, 0,
+                           (const asj_join_desc *)nullptr, slots, status);
+    return hipGetLastError();
+}
+
+hipError_t asj_launch_region_build_batch(const uint32_t *sig, int64_t m, const int64_t *r_seg, int32_t njoins,
+                                         const asj_join_desc *desc, const int32_t *win_r, const uint64_t *tot,
+                                         int64_t win_r_cap, const int32_t *rmap, int64_t rmap_cap, uint32_t *rcnt,
+                                         uint64_t *ovf, uint64_t *novf, uint64_t *slots, int32_t *status,
+                                         hipStream_t st)
+{
+    if (njoins < 1 || rmap_cap < 1 || !rmap || !rcnt || !ovf || !novf) return hipErrorInvalidValue;
+    uint32_t *nov = (uint32_t *)novf;
+    if (m > 0 && win_r_cap > 0) // a block per 64 build windows that may exist (the rest exit at once)
+        hipLaunchKernelGGL(region_scatter_batch_kernel, dim3((unsigned)((win_r_cap + kScatterWins - 1) / kScatterWins)),
+                           dim3(kPartBlock), 0, st, sig, m, r_seg, desc, win_r, tot, win_r_cap, rcnt, slots, ovf, nov,
+                           (const int32_t *)status);
+    // every region, rows or not: the segments get no other fill
+    hipLaunchKernelGGL(region_build_kernel<1>, dim3((unsigned)std::min<int64_t>(rmap_cap, 2048)), dim3(kRegionBlock),
+                       0, st, (const uint32_t *)rcnt, rmap_cap, 0, (uint64_t)0, 0, tot, rmap, desc, slots, ovf, nov,
+                       (const int32_t *)status);
+    if (m > 0)
+        hipLaunchKernelGGL(region_overflow_kernel<1>, dim3(64), dim3(256), 0, st, (const uint64_t *)ovf,
+                           (const uint32_t *)nov, (uint64_t)0, 0, r_seg, njoins, desc, slots, status);
     return hipGetLastError();
 }

@@ -57,6 +57,53 @@ def test_batch_matches_oracle_and_single_joins(A, oracle, wl, sched):
     assert start > 0 and (clock[:-1] >= start).all()
 
 
+def region_batch_joins(seed):
+    """Build sides whose segments have runs that leave their 4096-slot
+    regions: a key repeated 6000 times, a segment about 95% full, an empty
+    build side and a small join; every probe side holds each distinct build
+    key once (so that a row missing from its table loses its pair) plus
+    random keys."""
+    rng = np.random.default_rng(seed)
+
+    def rand(k):
+        lens = rng.integers(1, 24, size=k)
+        off = np.zeros(k + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, size=int(off[-1]), dtype=np.uint8).tobytes()
+        return [data[off[i]:off[i + 1]] for i in range(k)]
+
+    builds = [[b"same key"] * 6000 + rand(14000), [], rand(5000), rand(31000)]
+    joins = []
+    for rk in builds:
+        uniq = list(dict.fromkeys(rk))
+        joins.append((rk, [uniq[i] for i in rng.permutation(len(uniq))] + rand(500)))
+    return joins
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("sched", sorted(SCHED))
+def test_batch_segments_built_by_regions(A, oracle, wl, sched, plain):
+    """Batch segments are built region by region (rows scattered into the
+    4096-slot regions of their home slots, each region placed in LDS and
+    written whole, the rows that leave their region or find its slots all
+    taken placed afterwards from their home slot, wrapping at the segment's
+    end).  At load factor 0.95 one segment is about 95% full and another
+    holds a key repeated beyond a region's slots; every join must equal the
+    oracle's, with every build key probed."""
+    joins = region_batch_joins(11)
+    R, S, r_seg, s_seg = flatten(wl, joins)
+    flags = SCHED[sched] | (A.ASJ_PLAIN if plain else 0)
+    out, oseg, counts, cands, _ = A.join_batch(A.DeviceKeys.from_host(R), A.DeviceKeys.from_host(S), r_seg, s_seg,
+                                               flags=flags, load_factor=0.95)
+    outh = out.cpu().numpy()
+    for k, (rk, sk) in enumerate(joins):
+        want, want_cand = oracle.join_signature(wl.from_keys(rk), wl.from_keys(sk))
+        got = outh[oseg[k]:oseg[k] + counts[k]]
+        assert counts[k] == len(want) and np.array_equal(oracle.sort_pairs(got), want), k
+        if not plain:
+            assert cands[k] == want_cand, k
+
+
 def concat(wl, parts):
     """Workloads -> one batch: flattened relations (row-local ids) and segments."""
     def cat(rels):
