@@ -382,20 +382,21 @@ int asj_join_host_release(void);
 /* Outcome of an autotuning run. */
 typedef struct asj_tune_result {
     asj_opts best;    /* fastest options found (explicit values and schedule flag) */
-    float best_ms;    /* median time of one whole call with `best` */
-    float default_ms; /* median time with the defaults (0.5, 64, 2 rounds, fused) */
+    float best_ms;    /* time per call with `best`, over back-to-back calls */
+    float default_ms; /* the same with the defaults (0.5, 64, 2 rounds, fused) */
     int32_t trials;   /* configurations timed besides the defaults */
 } asj_tune_result;
 
-/* Autotuner for asj_join: times whole joins of r and s (one untimed and
- * three timed calls per configuration, median, HIP events on `stream`) over
+/* Autotuner for asj_join: times whole joins of r and s (one untimed call,
+ * then three back-to-back calls per configuration, HIP events on `stream`) over
  * the load factors {0.25, 0.35, 0.5, 0.7} that give distinct capacities,
  * keys_per_window {4, 8, 16, 32, 64}, both probe schedules and grid_rounds
  * {1, 2, 4}, with the signature parameters and ASJ_PLAIN / ASJ_NO_VERIFY /
  * ASJ_FINGERPRINT flags of `opts` (NULL = defaults; its load factor, keys
- * per window, grid rounds and schedule are ignored), and records the
- * fastest for later calls that leave these options to the library (see
- * asj_opts).  out, out_cap and out_count are the result buffers of the trial
+ * per window, grid rounds and schedule are ignored); times the four fastest
+ * again, each as two blocks of eight back-to-back calls, and records the
+ * fastest of those for later calls that leave these options to the library
+ * (see asj_opts).  out, out_cap and out_count are the result buffers of the trial
  * joins (as for asj_join); `res` (may be NULL) receives the outcome.
  * Synchronizes the stream.  Errors: those of asj_join, ASJ_EINVAL. */
 int asj_autotune(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pair *out, int64_t out_cap,

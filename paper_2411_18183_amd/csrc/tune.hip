@@ -51,6 +51,18 @@ constexpr float kLoadFactors[] = {0.25f, 0.35f, 0.5f, 0.7f};
 constexpr int kKeysPerWindow[] = {4, 8, 16, 32, 64};
 constexpr int kGridRounds[] = {1, 2, 4};
 constexpr int kReps = 3;
+// Grid pass: every configuration timed over kReps back-to-back calls.
+// Second stage: the kFinalists fastest of them and the defaults, timed again
+// as blocks of kBlockRuns back-to-back calls (one block each per pass,
+// kPasses passes in alternating order), so that the choice among
+// configurations a few percent apart does not rest on one short sample.
+// (The median of three single calls, each followed by a synchronization,
+// had picked windows of 4 keys for 4 KB keys, 7% slower than 64 when calls
+// follow each other, and 4 grid rounds for the large join, 3% slower
+// than 1.)
+constexpr int kFinalists = 4;
+constexpr int kBlockRuns = 8;
+constexpr int kPasses = 2;
 
 int64_t capacity_for(int64_t n, float lf)
 {
@@ -59,23 +71,37 @@ int64_t capacity_for(int64_t n, float lf)
     return cap;
 }
 
-// Median of kReps timed runs after one untimed run; the result of run() is
-// checked on every call.
+// Milliseconds per call over kReps back-to-back calls after one untimed
+// call (the result of run() is checked on every call).
 template <class Run>
 int time_runs(Run run, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms)
 {
     int rc = run();
     if (rc != ASJ_OK) return rc;
-    float t[kReps];
+    if (hipEventRecord(e0, st) != hipSuccess) return ASJ_EHIP;
     for (int i = 0; i < kReps; i++) {
-        if (hipEventRecord(e0, st) != hipSuccess) return ASJ_EHIP;
         rc = run();
         if (rc != ASJ_OK) return rc;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ASJ_EHIP;
-        if (hipEventElapsedTime(&t[i], e0, e1) != hipSuccess) return ASJ_EHIP;
     }
-    std::sort(t, t + kReps);
-    *ms = t[kReps / 2];
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ASJ_EHIP;
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return ASJ_EHIP;
+    *ms /= kReps;
+    return ASJ_OK;
+}
+
+// Milliseconds per call over kBlockRuns back-to-back calls (the stream
+// stays busy: no host round trip between them).
+template <class Run>
+int time_block(Run run, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    if (hipEventRecord(e0, st) != hipSuccess) return ASJ_EHIP;
+    for (int i = 0; i < kBlockRuns; i++) {
+        const int rc = run();
+        if (rc != ASJ_OK) return rc;
+    }
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return ASJ_EHIP;
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return ASJ_EHIP;
+    *ms /= kBlockRuns;
     return ASJ_OK;
 }
 
@@ -127,18 +153,45 @@ int tune(const asj_opts &base, int64_t n_build, bool batch, RunWith run_with, as
     float def_ms = 0.0f, best_ms = 0.0f;
     asj_opts best = defaults;
     int trials = 0;
+    // grid pass: ms per call of each configuration, the defaults first
+    struct Timed {
+        float ms;
+        asj_opts o;
+        bool is_default;
+    };
+    std::vector<Timed> timed;
     rc = time_runs([&] { return run_with(defaults); }, st, e0, e1, &def_ms);
-    best_ms = def_ms;
     if (rc == ASJ_OK) {
+        timed.push_back({def_ms, defaults, true});
         for (const asj_opts &o : grid(base, n_build, batch)) {
             float ms = 0.0f;
             rc = time_runs([&] { return run_with(o); }, st, e0, e1, &ms);
             if (rc != ASJ_OK) break;
             trials++;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = o;
+            timed.push_back({ms, o, false});
+        }
+    }
+    if (rc == ASJ_OK) { // second stage: the finalists and the defaults, on one measure
+        std::stable_sort(timed.begin(), timed.end(), [](const Timed &x, const Timed &y) { return x.ms < y.ms; });
+        std::vector<size_t> fin;
+        for (size_t i = 0; i < timed.size(); i++)
+            if ((int)fin.size() < kFinalists || timed[i].is_default) fin.push_back(i);
+        std::vector<float> sum(fin.size(), 0.0f);
+        for (int pass = 0; pass < kPasses && rc == ASJ_OK; pass++)
+            for (size_t i = 0; i < fin.size() && rc == ASJ_OK; i++) {
+                const size_t k = pass % 2 ? fin.size() - 1 - i : i;
+                float ms = 0.0f;
+                rc = time_block([&] { return run_with(timed[fin[k]].o); }, st, e0, e1, &ms);
+                sum[k] += ms;
             }
+        if (rc == ASJ_OK) {
+            size_t bi = 0;
+            for (size_t i = 0; i < fin.size(); i++) {
+                if (sum[i] < sum[bi]) bi = i;
+                if (timed[fin[i]].is_default) def_ms = sum[i] / kPasses;
+            }
+            best = timed[fin[bi]].o;
+            best_ms = sum[bi] / kPasses;
         }
     }
     (void)hipEventDestroy(e0);
