@@ -55,11 +55,9 @@ constexpr int kReps = 3;
 // Second stage: the kFinalists fastest of them and the defaults, timed again
 // as blocks of kBlockRuns back-to-back calls (one block each per pass,
 // kPasses passes in alternating order), so that the choice among
-// configurations a few percent apart does not rest on one short sample.
-// (The median of three single calls, each followed by a synchronization,
-// had picked windows of 4 keys for 4 KB keys, 7% slower than 64 when calls
-// follow each other, and 4 grid rounds for the large join, 3% slower
-// than 1.)
+// configurations a few percent apart does not rest on one short sample
+// (the minimum over some sixty medians of three single calls, each call
+// followed by a synchronization, had often been a lucky sample).
 constexpr int kFinalists = 4;
 constexpr int kBlockRuns = 8;
 constexpr int kPasses = 2;
