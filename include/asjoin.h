@@ -113,8 +113,8 @@ extern "C" {
                                 use device-memory tables. */
 #define ASJ_LOCAL_ONLY 0x1000u /* asj_join_batch (and asj_autotune_batch): the caller states that
                                 every join has at most 10240 build rows, so every join is probed
-                                against an LDS table and the device-memory table build (two
-                                launches that would find nothing to insert) is skipped.  Checked
+                                against an LDS table and the device-memory table build (three
+                                launches that would find nothing to build) is skipped.  Checked
                                 on the device: a join above the limit fails the call as invalid
                                 segments do (every count -1, no key read).  With
                                 ASJ_GLOBAL_TABLES or ASJ_PROBE_SPLIT: ASJ_EINVAL (an automatic
