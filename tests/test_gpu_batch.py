@@ -104,6 +104,45 @@ def test_batch_segments_built_by_regions(A, oracle, wl, sched, plain):
             assert cands[k] == want_cand, k
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_batch_random_shapes_built_by_regions(A, oracle, wl, seed):
+    """Seeded batches of 2-40 joins whose build sides are empty, a few rows,
+    around the LDS-table limit or up to 60k rows (some with a fifth of their
+    rows on three repeated keys), at load factors from 0.25 to 0.97, under
+    every schedule: each join equals the oracle's, with its candidate count;
+    every distinct build key is probed."""
+    rng = np.random.default_rng([seed, 41])
+
+    def keys(k, hot=None, dup=0.0):
+        lens = rng.integers(1, 21, size=k)
+        off = np.zeros(k + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, size=int(off[-1]), dtype=np.uint8).tobytes()
+        out = [data[off[i]:off[i + 1]] for i in range(k)]
+        for i in np.flatnonzero(rng.uniform(size=k) < dup):
+            out[i] = hot[int(rng.integers(0, len(hot)))]
+        return out
+
+    joins = []
+    for _ in range(int(rng.integers(2, 41))):
+        nr = int(rng.choice([0, int(rng.integers(1, 200)), int(rng.integers(5000, 15000)),
+                             int(rng.integers(20000, 60000))]))
+        rk = keys(nr, keys(3), float(rng.choice([0.0, 0.2])))
+        uniq = list(dict.fromkeys(rk))
+        joins.append((rk, [uniq[i] for i in rng.permutation(len(uniq))] + keys(int(rng.integers(0, 300)))))
+    R, S, r_seg, s_seg = flatten(wl, joins)
+    lf = float(rng.choice([0.25, 0.5, 0.9, 0.97]))
+    wants = [oracle.join_signature(wl.from_keys(rk), wl.from_keys(sk)) for rk, sk in joins]
+    for sched in sorted(SCHED):
+        out, oseg, counts, cands, _ = A.join_batch(A.DeviceKeys.from_host(R), A.DeviceKeys.from_host(S), r_seg, s_seg,
+                                                   flags=SCHED[sched], load_factor=lf)
+        outh = out.cpu().numpy()
+        for k, (want, want_cand) in enumerate(wants):
+            got = outh[oseg[k]:oseg[k] + counts[k]]
+            assert counts[k] == len(want) and np.array_equal(oracle.sort_pairs(got), want), (sched, k)
+            assert cands[k] == want_cand, (sched, k)
+
+
 def concat(wl, parts):
     """Workloads -> one batch: flattened relations (row-local ids) and segments."""
     def cat(rels):
