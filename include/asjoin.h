@@ -196,8 +196,12 @@ int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hip
  *   r          build relation (borrowed by the table, see asj_table)
  *   opts       may be NULL (defaults)
  *   table_out  receives the new table (host pointer to a handle)
- * The slot array is allocated stream-ordered on `stream`.  Whether every row
- * found a slot is known only on the device: asj_table_status() reports it.
+ * The slot array is allocated stream-ordered on `stream`: 8 bytes per slot,
+ * 4 per build row for the signatures (8 with 64-bit signatures), and, for
+ * the tables of 327680 rows or more that are built region by region, 8 more
+ * per row and 4 per 4096 slots of build scratch, all held until
+ * asj_table_free.  Whether every row found a slot is known only on the
+ * device: asj_table_status() reports it.
  * Errors: ASJ_EINVAL, ASJ_EUNSUPPORTED, ASJ_ENOMEM, ASJ_EHIP. */
 int asj_build(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t stream);
 
