@@ -199,7 +199,7 @@ int asj_signature(const asj_keys *keys, asj_sig_params p, uint32_t *sig_out, hip
  * The slot array is allocated stream-ordered on `stream`: 8 bytes per slot,
  * 4 per build row for the signatures (8 with 64-bit signatures), and, for
  * the tables of 327680 rows or more that are built region by region, 8 more
- * per row and 4 per 4096 slots of build scratch, all held until
+ * per row and at most 33 KB of build scratch, all held until
  * asj_table_free.  Whether every row found a slot is known only on the
  * device: asj_table_status() reports it.
  * Errors: ASJ_EINVAL, ASJ_EUNSUPPORTED, ASJ_ENOMEM, ASJ_EHIP. */
