@@ -202,7 +202,10 @@ hipError_t alloc_async(T **p, size_t count, hipStream_t st)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t st)
+// zc0, zc1 (may be NULL): counters of a probe that follows on the stream,
+// cleared by the build's first launch (asj_join: one launch fewer).
+int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, hipStream_t st,
+               int64_t *zc0 = nullptr, int64_t *zc1 = nullptr)
 {
     if (!table_out || !keys_ok(r)) return ASJ_EINVAL;
     *table_out = nullptr;
@@ -275,8 +278,8 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
     do {
         hipError_t le;
         tim_begin("table_init", st);
-        le = region ? asj_launch_region_init(region, r->n, cap, t->status, st)
-                    : asj_launch_table_init(t->slots, cap, t->status, st);
+        le = region ? asj_launch_region_init(region, r->n, cap, t->status, st, zc0, zc1)
+                    : asj_launch_table_init(t->slots, cap, t->status, st, zc0, zc1);
         if (le == hipSuccess && t->validate) le = asj_launch_validate(r->offsets, r->n, t->status, st);
         tim_end(st);
         if (le != hipSuccess) { out_rc = hip_fail(le); break; }
@@ -301,12 +304,13 @@ int build_impl(const asj_keys *r, const asj_opts *opts, asj_table **table_out, h
 }
 
 int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
-                   int64_t *cand_count, hipStream_t st);
+                   int64_t *cand_count, hipStream_t st, bool zeroed);
 
+// zeroed: the counters were cleared earlier on the stream (by the build).
 int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
-               int64_t *cand_count, hipStream_t st)
+               int64_t *cand_count, hipStream_t st, bool zeroed = false)
 {
-    int rc = probe_unsorted(t, s, out, out_cap, out_count, cand_count, st);
+    int rc = probe_unsorted(t, s, out, out_cap, out_count, cand_count, st, zeroed);
     if (rc != ASJ_OK || !t->sorted || out_cap == 0) return rc;
     void *sort_tmp = nullptr;
     hipError_t e = hipMallocAsync(&sort_tmp, asj_sort_scratch_bytes(out_cap), st);
@@ -319,13 +323,13 @@ int probe_impl(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out
 }
 
 int probe_unsorted(const asj_table *t, const asj_keys *s, asj_pair *out, int64_t out_cap, int64_t *out_count,
-                   int64_t *cand_count, hipStream_t st)
+                   int64_t *cand_count, hipStream_t st, bool zeroed)
 {
     if (!t || !keys_ok(s) || !out_count || out_cap < 0 || (out_cap > 0 && !out)) return ASJ_EINVAL;
     int dev = 0;
     int rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;
-    hipError_t e = asj_launch_zero2(out_count, cand_count, st);
+    hipError_t e = zeroed ? hipSuccess : asj_launch_zero2(out_count, cand_count, st);
     if (e != hipSuccess) return hip_fail(e);
     asj_probe_args a = {};
     a.rdata = t->r.data;
@@ -701,9 +705,9 @@ int asj_join(const asj_keys *r, const asj_keys *s, const asj_opts *opts, asj_pai
     const int lrc = join_local_single(r, s, opts, out, out_cap, out_count, cand_count, st);
     if (lrc != kNotLocal) return lrc;
     asj_table *t = nullptr;
-    int rc = build_impl(r, opts, &t, st);
+    int rc = build_impl(r, opts, &t, st, out_count, cand_count); // the build's first launch clears the counters
     if (rc != ASJ_OK) return rc;
-    rc = probe_impl(t, s, out, out_cap, out_count, cand_count, st);
+    rc = probe_impl(t, s, out, out_cap, out_count, cand_count, st, true);
     int rc2 = table_free_impl(t);
     return rc != ASJ_OK ? rc : rc2;
 }

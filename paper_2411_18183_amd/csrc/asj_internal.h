@@ -323,8 +323,10 @@ hipError_t asj_launch_validate(const int64_t *off, int64_t n, int32_t *status, h
 hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t st);
 hipError_t asj_launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
-// slots[0 .. cap) = empty and *status = ASJ_OK in one launch.
-hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st);
+// slots[0 .. cap) = empty and *status = ASJ_OK in one launch (and *z0, *z1 =
+// 0 where not NULL: the counters of the probe that follows).
+hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st,
+                                 int64_t *z0 = nullptr, int64_t *z1 = nullptr);
 // *a = 0 and, when b is not NULL, *b = 0 in one launch.
 hipError_t asj_launch_zero2(int64_t *a, int64_t *b, hipStream_t st);
 hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, uint64_t mask,
@@ -339,7 +341,8 @@ hipError_t asj_launch_insert(const uint32_t *sig, int64_t m, int plain, uint64_t
 // there: the build writes every slot) and sets *status = ASJ_OK;
 // asj_launch_region_build then fills slots[0 .. cap) from the signatures.
 int64_t asj_region_scratch_bytes(int64_t m, int64_t cap);
-hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st);
+hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st,
+                                  int64_t *z0 = nullptr, int64_t *z1 = nullptr);
 hipError_t asj_launch_region_build(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, int64_t cap,
                                    int32_t *status, void *scratch, hipStream_t st);
 
@@ -531,10 +534,10 @@ hipError_t asj_launch_probe(const asj_probe_args *a, int mode, int nsym, const u
 // table); a->table_status must point to a cleared status word.
 hipError_t asj_launch_probe_local_single(const asj_probe_args *a, int mode, int nsym, const uint16_t *tab,
                                          hipStream_t st);
-// Clears the two counters (b may be NULL), sets *status = ASJ_OK and clears
+// Clears the counters (b and c may be NULL), sets *status = ASJ_OK and clears
 // words[0 .. nwords) (may be NULL), in one launch.
 hipError_t asj_launch_local_init(int64_t *a, int64_t *b, int32_t *status, uint32_t *words, int64_t nwords,
-                                 hipStream_t st);
+                                 hipStream_t st, int64_t *c = nullptr);
 // Right and full outer joins: (r_id, -1) for every build row r < m with
 // rmatch[r] == 0, appended to the output like the probe kernel's pairs.
 // Batch (njoins > 0): row r belongs to join j with r_seg[j] <= r <

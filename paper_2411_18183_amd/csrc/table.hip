@@ -49,10 +49,15 @@ __global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v)
 }
 
 // A new table: every slot empty and the status word cleared, in one launch.
-__global__ void table_init_kernel(uint64_t *__restrict__ slots, int64_t cap, int32_t *__restrict__ status)
+__global__ void table_init_kernel(uint64_t *__restrict__ slots, int64_t cap, int32_t *__restrict__ status,
+                                  int64_t *__restrict__ z0, int64_t *__restrict__ z1)
 {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i0 == 0) *status = ASJ_OK;
+    if (i0 == 0) {
+        *status = ASJ_OK;
+        if (z0) *z0 = 0;
+        if (z1) *z1 = 0;
+    }
     for (int64_t i = i0; i < cap; i += (int64_t)gridDim.x * blockDim.x) slots[i] = ASJ_EMPTY_SLOT;
 }
 
@@ -65,13 +70,14 @@ __global__ void zero2_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b)
 
 // Counters, status word and a word array cleared in one launch (see
 // asj_launch_local_init).
-__global__ void local_init_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b, int32_t *__restrict__ status,
-                                  uint32_t *__restrict__ words, int64_t nwords)
+__global__ void local_init_kernel(int64_t *__restrict__ a, int64_t *__restrict__ b, int64_t *__restrict__ c,
+                                  int32_t *__restrict__ status, uint32_t *__restrict__ words, int64_t nwords)
 {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 == 0) {
         *a = 0;
         if (b) *b = 0;
+        if (c) *c = 0;
         *status = ASJ_OK;
     }
     if (words)
@@ -368,18 +374,19 @@ hipError_t asj_launch_fill64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st)
+hipError_t asj_launch_table_init(uint64_t *slots, int64_t cap, int32_t *status, hipStream_t st, int64_t *z0,
+                                 int64_t *z1)
 {
     hipLaunchKernelGGL(table_init_kernel, dim3(grid_for(cap > 0 ? cap : 1, 256, 16384)), dim3(256), 0, st, slots, cap,
-                       status);
+                       status, z0, z1);
     return hipGetLastError();
 }
 
 hipError_t asj_launch_local_init(int64_t *a, int64_t *b, int32_t *status, uint32_t *words, int64_t nwords,
-                                 hipStream_t st)
+                                 hipStream_t st, int64_t *c)
 {
     const int g = grid_for(nwords > 0 ? nwords : 1, 256, 4096);
-    hipLaunchKernelGGL(local_init_kernel, dim3(g), dim3(256), 0, st, a, b, status, words, nwords);
+    hipLaunchKernelGGL(local_init_kernel, dim3(g), dim3(256), 0, st, a, b, c, status, words, nwords);
     return hipGetLastError();
 }
 
@@ -462,11 +469,12 @@ int64_t asj_region_scratch_bytes(int64_t m, int64_t cap)
     return region_plan(m, cap, nullptr, &L) ? L.bytes : -1;
 }
 
-hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st)
+hipError_t asj_launch_region_init(void *scratch, int64_t m, int64_t cap, int32_t *status, hipStream_t st,
+                                  int64_t *z0, int64_t *z1)
 {
     region_layout L;
     if (!scratch || !region_plan(m, cap, (uint8_t *)scratch, &L)) return hipErrorInvalidValue;
-    return asj_launch_local_init((int64_t *)L.novf, nullptr, status, L.cnt, L.nreg, st);
+    return asj_launch_local_init((int64_t *)L.novf, z0, status, L.cnt, L.nreg, st, z1);
 }
 
 hipError_t asj_launch_region_build(const uint32_t *sig, int64_t m, int plain, uint64_t *slots, int64_t cap,
