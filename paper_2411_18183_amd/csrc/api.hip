@@ -426,7 +426,10 @@ struct BatchLayout {
     int64_t slot_bound, win_r_cap, win_s_cap, region_cap;
 };
 
-bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf, BatchLayout *L)
+// local_only: every join has an LDS table, so no device table is built and
+// the layout holds no region-build scratch.
+bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf, BatchLayout *L,
+                  bool local_only = false)
 {
     if (J < 1 || n_build < 0 || n_probe < 0 || kpw < 1 || !(lf > 0.0f && lf < 1.0f)) return false;
     // every segment has capacity 64 or less than 2 |R_j| / lf
@@ -435,7 +438,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     L->win_r_cap = n_build / ASJ_WAVE + J + 1;
     L->win_s_cap = n_probe / kpw + J + 1;
     // table regions of 64 slots or more each
-    L->region_cap = L->slot_bound / 64 + 1;
+    L->region_cap = local_only ? 0 : L->slot_bound / 64 + 1;
     size_t off = 0;
     L->desc = off;
     off = align256(off + sizeof(asj_join_desc) * (size_t)J);
@@ -467,7 +470,7 @@ bool batch_layout(int32_t J, int64_t n_build, int64_t n_probe, int kpw, float lf
     L->novf = off;
     off = align256(off + sizeof(uint64_t));
     L->ovf = off;
-    off = align256(off + sizeof(uint64_t) * (size_t)(n_build > 0 ? n_build : 1));
+    if (!local_only) off = align256(off + sizeof(uint64_t) * (size_t)(n_build > 0 ? n_build : 1));
     L->bytes = off;
     return true;
 }
@@ -818,12 +821,14 @@ int asj_util_copy(void *dst, const void *src, int64_t bytes, hipStream_t st)
 
 int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts)
 {
-    int plain, verify, kpw, split;
+    int plain, verify, kpw, split, local_only = 0;
     asj_sig_params sig;
     float lf;
-    if (batch_opts(opts, n_build, &plain, &verify, &sig, &lf, &kpw, &split) != ASJ_OK) return -1;
+    if (batch_opts(opts, n_build, &plain, &verify, &sig, &lf, &kpw, &split, nullptr, nullptr, nullptr, nullptr,
+                   &local_only) != ASJ_OK)
+        return -1;
     BatchLayout L;
-    if (!batch_layout(njoins, n_build, n_probe, kpw, lf, &L)) return -1;
+    if (!batch_layout(njoins, n_build, n_probe, kpw, lf, &L, local_only != 0)) return -1;
     return (int64_t)L.bytes;
 }
 
@@ -843,7 +848,7 @@ int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t st)
     if (rc != ASJ_OK) return rc;
     if (split) local = 0; // the split schedule signs the probe keys first: device-memory tables only
     BatchLayout L;
-    if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L)) return ASJ_EINVAL;
+    if (!batch_layout(b->njoins, b->r.n, b->s.n, kpw, lf, &L, local_only != 0)) return ASJ_EINVAL;
     int dev = 0;
     rc = ensure_init(&dev);
     if (rc != ASJ_OK) return rc;

@@ -24,6 +24,7 @@ constexpr int kPlanBlock = 1024;
 // decreasing), segments that would not fit slot_cap slots, or (local_only)
 // a join too large for an LDS table, set *status to ASJ_EINVAL so that no
 // later kernel of the batch touches the slots or reads a key.
+template <int Q> // scanned quantities: 5, or 4 without table regions (no device table is built)
 __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *__restrict__ r_seg,
                                                                 const int64_t *__restrict__ s_seg, int32_t J,
                                                                 int64_t n_r, int64_t n_s, int64_t slot_cap, float lf,
@@ -37,7 +38,6 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
                                                                 uint32_t *__restrict__ rcnt, int64_t rcnt_cap,
                                                                 uint64_t *__restrict__ novf)
 {
-    constexpr int Q = 5; // scanned quantities
     constexpr int kWaves = kPlanBlock / ASJ_WAVE;
     __shared__ uint64_t wtot[Q][kWaves]; // per-wave totals of the current pass
     __shared__ uint64_t carry[Q];
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
     __syncthreads();
     for (int base = 0; base < J; base += kPlanBlock) {
         const int j = base + tid;
-        uint64_t v[Q] = {0, 0, 0, 0, 0};
+        uint64_t v[5] = {0, 0, 0, 0, 0};
         if (j < J) {
             if (r_seg[j + 1] < r_seg[j] || s_seg[j + 1] < s_seg[j]) bad = 1;
             const int64_t nr = max((int64_t)0, r_seg[j + 1] - r_seg[j]);
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
                 v[0] = cap;
                 v[1] = (uint64_t)((nr + ASJ_WAVE - 1) / ASJ_WAVE);
                 v[2] = nw;
-                v[4] = cap >> asj_seg_region_bits(cap);
+                if (Q > 4) v[4] = cap >> asj_seg_region_bits(cap);
             }
         }
         // inclusive scans: within each wave by shuffles, then over the
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
             desc[j].wbase_r = (int64_t)(carry[1] + inc[1] - v[1]);
             desc[j].wbase = (int64_t)(carry[2] + inc[2] - v[2]);
             desc[j].wbase_l = (int64_t)(carry[3] + inc[3] - v[3]);
-            desc[j].rbase = (int64_t)(carry[4] + inc[4] - v[4]);
+            desc[j].rbase = Q > 4 ? (int64_t)(carry[Q > 4 ? 4 : 0] + inc[Q > 4 ? 4 : 0] - v[4]) : 0;
             rows_done[j] = 0;
             out_count[j] = 0;
             if (cand_count) cand_count[j] = 0;
@@ -106,12 +106,15 @@ __global__ __launch_bounds__(kPlanBlock) void batch_plan_kernel(const int64_t *_
         }
         __syncthreads();
     }
-    // (carry is final: its last update was followed by a barrier)
-    if (rcnt && carry[4] > (uint64_t)rcnt_cap) bad = 1; // (only with more slots than slot_cap as well)
-    __syncthreads();
+    if constexpr (Q > 4) {
+        // (carry is final: its last update was followed by a barrier)
+        if (rcnt && carry[4] > (uint64_t)rcnt_cap) bad = 1; // (only with more slots than slot_cap as well)
+        __syncthreads();
+    }
     if (tid < Q) tot[tid] = bad ? 0 : carry[tid];
-    if (rcnt && !bad) { // region counts and the overflow count of a build by regions
-        for (uint64_t i = tid; i < carry[4]; i += kPlanBlock) rcnt[i] = 0u;
+    if (Q == 4 && tid == 4) tot[4] = 0; // no table regions
+    if (Q > 4 && rcnt && !bad) { // region counts and the overflow count of a build by regions
+        for (uint64_t i = tid; i < carry[Q > 4 ? 4 : 0]; i += kPlanBlock) rcnt[i] = 0u;
         if (tid == 0) *novf = 0;
     }
     if (tid == 0) {
@@ -145,9 +148,14 @@ hipError_t asj_launch_batch_plan(const int64_t *r_seg, const int64_t *s_seg, int
 {
     if (keys_per_window < 1 || keys_per_window > ASJ_WAVE) return hipErrorInvalidValue;
     if (rcnt && !novf) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s, slot_cap,
-                       load_factor, keys_per_window, local_rows, local_only, desc, rows_done, out_count, cand_count,
-                       done_clock, tot, status, rcnt, rcnt_cap, novf);
+    if (local_only) // every join gets an LDS table: no table regions to number
+        hipLaunchKernelGGL(batch_plan_kernel<4>, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s,
+                           slot_cap, load_factor, keys_per_window, local_rows, local_only, desc, rows_done, out_count,
+                           cand_count, done_clock, tot, status, (uint32_t *)nullptr, (int64_t)0, (uint64_t *)nullptr);
+    else
+        hipLaunchKernelGGL(batch_plan_kernel<5>, dim3(1), dim3(kPlanBlock), 0, st, r_seg, s_seg, njoins, n_r, n_s,
+                           slot_cap, load_factor, keys_per_window, local_rows, local_only, desc, rows_done, out_count,
+                           cand_count, done_clock, tot, status, rcnt, rcnt_cap, novf);
     return hipGetLastError();
 }
 
