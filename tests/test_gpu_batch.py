@@ -327,6 +327,36 @@ def test_batch_local_only_flag(A, oracle, wl, kind):
             A.join_batch(R, S, r_seg, s_seg, caps=caps, flags=flags | extra)
 
 
+def test_batch_local_only_workspace(A, oracle, wl):
+    """A batch that states ASJ_LOCAL_ONLY builds no device table, so its
+    workspace needs no table-build scratch: asj_batch_workspace_bytes gives
+    less with the flag, a caller workspace of exactly that size serves the
+    flagged batch (equal to the oracle), and the same batch without the flag
+    refuses it as too small."""
+    import torch
+    parts = [wl.fixed_length(seed=110 + i, m=m, n=n, key_len=L, copy_frac=0.3)
+             for i, (m, n, L) in enumerate([(3000, 4000, 20), (10240, 9000, 64), (500, 800, 9)])]
+    Rf, Sf, r_seg, s_seg = concat(wl, parts)
+    R, S = A.DeviceKeys.from_host(Rf), A.DeviceKeys.from_host(Sf)
+    J, opts = len(parts), dict(load_factor=0.5, keys_per_window=32)
+    small = A.asj_batch_workspace_bytes(J, R.n, S.n, flags=A.ASJ_LOCAL_ONLY, **opts)
+    assert small < A.asj_batch_workspace_bytes(J, R.n, S.n, **opts)
+    dev = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int64)).cuda()
+    caps = np.diff(s_seg) + 16
+    oseg = np.concatenate([[0], np.cumsum(caps)])
+    out = torch.empty((int(oseg[-1]), 2), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(J, dtype=torch.int64, device="cuda")
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    A.asj_join_batch(R, S, dev(r_seg), dev(s_seg), out, dev(oseg), counts, workspace=ws, flags=A.ASJ_LOCAL_ONLY,
+                     **opts)
+    c, outh = counts.cpu().numpy(), out.cpu().numpy()
+    for k, w in enumerate(parts):
+        want = oracle.join_signature(w.R, w.S)[0]
+        assert c[k] == len(want) and np.array_equal(oracle.sort_pairs(outh[oseg[k]:oseg[k] + c[k]]), want), k
+    with pytest.raises(A.AsjError):
+        A.asj_join_batch(R, S, dev(r_seg), dev(s_seg), out, dev(oseg), counts, workspace=ws, **opts)
+
+
 @pytest.mark.parametrize("sig", [(16, 1), (8, 2), (8, 4)])
 @pytest.mark.parametrize("verify", [True, False])
 def test_batch_lds_tables_other_signatures(A, oracle, wl, sig, verify):
