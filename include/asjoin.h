@@ -307,7 +307,9 @@ typedef struct asj_batch {
 
 /* Device workspace needed by asj_join_batch for njoins joins over n_build
  * build rows and n_probe probe rows with these options (NULL = defaults);
- * -1 on bad arguments. */
+ * -1 on bad arguments.  With ASJ_LOCAL_ONLY in the options the table-build
+ * scratch (about 8 bytes per build row) is left out, and a workspace of that
+ * size serves only calls that pass the flag (others refuse it: ASJ_EINVAL). */
 int64_t asj_batch_workspace_bytes(int32_t njoins, int64_t n_build, int64_t n_probe, const asj_opts *opts);
 
 int asj_join_batch(const asj_batch *b, const asj_opts *opts, hipStream_t stream);
