@@ -133,3 +133,22 @@ def test_noalloc_refuses_oversized_build_side_before_device_work(lib):
     assert lib.asj_join_noalloc(ctypes.byref(r), ctypes.byref(s), None, None, ctypes.c_int64(0),
                                 ctypes.byref(cnt), None, None) == -1
     assert lib.asj_join_noalloc(None, None, None, None, ctypes.c_int64(0), None, None, None) == -1
+
+
+def test_batch_workspace_sizing_on_the_host(lib):
+    """asj_batch_workspace_bytes is host arithmetic: it grows with the
+    relations, refuses bad arguments (-1), and leaves the table-build scratch
+    (8 bytes per build row at least) out for ASJ_LOCAL_ONLY batches, whose
+    workspace is then too small for the same batch without the flag."""
+    lib.asj_batch_workspace_bytes.restype = ctypes.c_int64
+    lib.asj_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    ws = lambda J, m, n, **kw: lib.asj_batch_workspace_bytes(J, m, n, ctypes.byref(_Opts(**{
+        "f": 16, "nsym": 2, "load_factor": 0.5, "flags": 0, "keys_per_window": 32, "grid_rounds": 0, **kw})))
+    small, large = ws(3, 100000, 120000), ws(3, 200000, 120000)
+    assert 0 < small < large
+    local = ws(3, 100000, 120000, flags=0x1000)  # ASJ_LOCAL_ONLY
+    assert 0 < local and small - local >= 8 * 100000
+    assert ws(0, 10, 10) == -1                     # no joins
+    assert ws(3, -1, 10) == -1                     # negative row count
+    assert ws(3, 10, 10, load_factor=1.5) == -1    # load factor out of (0, 1)
+    assert ws(3, 10, 10, flags=0x1000 | 0x400) == -1  # ASJ_LOCAL_ONLY with ASJ_GLOBAL_TABLES
