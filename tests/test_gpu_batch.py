@@ -80,6 +80,36 @@ def region_batch_joins(seed):
     return joins
 
 
+def test_batch_segment_with_more_regions_than_a_block_counts(A, oracle, wl):
+    """A segment of 2^27 slots (700k build rows at load factor 0.01) has
+    32768 regions: a partition block counts the first 8192 regions from its
+    first row's in LDS and takes one device atomic per row for the others.
+    Beside it, a small join; both equal the oracle, every build key probed."""
+    rng = np.random.default_rng(77)
+
+    def keys(k):
+        lens = rng.integers(1, 24, size=k)
+        off = np.zeros(k + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        data = rng.integers(0, 256, size=int(off[-1]), dtype=np.uint8).tobytes()
+        return [data[off[i]:off[i + 1]] for i in range(k)]
+
+    joins = []
+    for nr in (700_000, 20_000):
+        rk = keys(nr) + [b"hot key"] * 50
+        uniq = list(dict.fromkeys(rk))
+        joins.append((rk, [uniq[i] for i in rng.permutation(len(uniq))] + keys(1000)))
+    R, S, r_seg, s_seg = flatten(wl, joins)
+    out, oseg, counts, cands, _ = A.join_batch(A.DeviceKeys.from_host(R), A.DeviceKeys.from_host(S), r_seg, s_seg,
+                                               flags=SCHED["fused_global"], load_factor=0.01)
+    outh = out.cpu().numpy()
+    for k, (rk, sk) in enumerate(joins):
+        want, want_cand = oracle.join_signature(wl.from_keys(rk), wl.from_keys(sk))
+        got = outh[oseg[k]:oseg[k] + counts[k]]
+        assert counts[k] == len(want) and np.array_equal(oracle.sort_pairs(got), want), k
+        assert cands[k] == want_cand, k
+
+
 @pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("sched", sorted(SCHED))
 def test_batch_segments_built_by_regions(A, oracle, wl, sched, plain):
