@@ -655,6 +655,19 @@ def test_device_table_every_row_found(A, oracle, wl, case, sched, plain):
     assert total == len(want) and np.array_equal(oracle.sort_pairs(got), want)
     if not plain:
         assert ncand == want_cand
+    if case == "one_key" and sched == "split":
+        # a build side that fails validation: the region build places no row
+        # (but still writes every region), the table reports ASJ_EINVAL and
+        # a probe of it yields -1
+        t = A.asj_build(A.DeviceKeys.from_host(swapped(wl, R, 1000)), flags=flags | A.ASJ_VALIDATE,
+                        load_factor=lf)
+        assert t.status() == A.ASJ_EINVAL
+        import torch
+        out = torch.empty((S.n, 2), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        A.asj_probe(t, A.DeviceKeys.from_host(S), out, cnt)
+        assert int(cnt[0]) == -1
+        t.free()
 
 
 @pytest.mark.parametrize("m", [10239, 10240, 10241])
